@@ -1,0 +1,135 @@
+"""Seeded input generators (numpy PCG64), all produced in fp64.
+
+Matrices
+--------
+sym_gaussian(n, seed)        A = (G + G^T)/2, G_ij ~ N(0, 1)
+herm_gaussian(n, seed)       A = (G + G^H)/2, Re G_ij, Im G_ij ~ N(0, 1/2)
+haar_spectrum(n, sq, sl)     A = Q diag(lambda) Q^T, Q Haar orthogonal (QR of a
+                             Gaussian with diag(R) > 0), lambda ~ U[-1, 1]
+
+Back-transformation inputs (boundary layout of the reflectors)
+--------------------------------------------------------------
+reflector_layout(n, b)       sweep, chase step, row start and length per slot
+synthetic_reflectors(...)    random unit-norm-preserving Householder reflectors
+                             laid out as the band->tridiagonal chase emits them
+gaussian_block(n, nev, ...)  a dense n x nev block standing in for eigenvectors
+
+The synthetic reflectors have the structure of the real ones: v[0] = 1, the
+other L-1 entries of size about 1/sqrt(b), zero padding past L, and a tau that
+makes H = I - tau v v^H exactly orthogonal / unitary up to the rounding of tau
+(real: tau = 2/||v||^2, tau = 0 for L = 1 like LAPACK; complex:
+tau = (1 - e^{i theta})/||v||^2).  The values a real bulge chase would produce
+differ, the shapes, sizes, slot structure and magnitudes do not.
+"""
+import numpy as np
+
+__all__ = [
+    "sym_gaussian", "herm_gaussian", "haar_spectrum", "reflector_layout",
+    "synthetic_reflectors", "gaussian_block", "to_dtype",
+    "batched_sizes", "scf_sequence_sizes",
+]
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def sym_gaussian(n, seed):
+    G = _rng(seed).standard_normal((n, n))
+    return (G + G.T) / 2.0
+
+
+def herm_gaussian(n, seed):
+    g = _rng(seed)
+    s = np.sqrt(0.5)
+    G = g.standard_normal((n, n)) * s + 1j * (g.standard_normal((n, n)) * s)
+    return (G + G.conj().T) / 2.0
+
+
+def haar_spectrum(n, seed_q, seed_l):
+    X = _rng(seed_q).standard_normal((n, n))
+    Qh, R = np.linalg.qr(X)
+    Qh = Qh * np.sign(np.diag(R))[None, :]
+    lam = _rng(seed_l).uniform(-1.0, 1.0, n)
+    A = (Qh * lam[None, :]) @ Qh.T
+    return (A + A.T) / 2.0
+
+
+def reflector_layout(n, b):
+    """Per-slot (s, j, r, L) arrays in generation order (s, then j)."""
+    if n < 2:
+        z = np.zeros(0, dtype=np.int64)
+        return z, z, z, z
+    s = np.arange(n - 1, dtype=np.int64)
+    J = (n - 1 - s + b - 1) // b
+    off = np.concatenate([[0], np.cumsum(J)[:-1]])
+    ss = np.repeat(s, J)
+    jj = np.arange(int(J.sum()), dtype=np.int64) - np.repeat(off, J)
+    rr = ss + 1 + jj * b
+    LL = np.minimum(b, n - rr)
+    return ss, jj, rr, LL
+
+
+def synthetic_reflectors(n, b, complex_=False, seed=0, chunk=1 << 18):
+    """Random Householder reflectors in the boundary layout.
+
+    Returns (hh, tau): hh has shape (nrefl*b,), tau (nrefl,), fp64 or complex128.
+    """
+    _, _, _, LL = reflector_layout(n, b)
+    N = LL.size
+    g = _rng(seed)
+    dt = np.complex128 if complex_ else np.float64
+    hh = np.zeros((N, b), dtype=dt)
+    tau = np.zeros(N, dtype=dt)
+    col = np.arange(b)[None, :]
+    sc = 1.0 / np.sqrt(b)
+    for a in range(0, N, chunk):
+        e = min(N, a + chunk)
+        m = e - a
+        if complex_:
+            h = np.sqrt(0.5) * sc
+            v = g.standard_normal((m, b)) * h + 1j * (g.standard_normal((m, b)) * h)
+        else:
+            v = g.standard_normal((m, b)) * sc
+        v[:, 0] = 1.0
+        v[col >= LL[a:e, None]] = 0.0
+        nrm2 = np.sum(np.abs(v) ** 2, axis=1)
+        if complex_:
+            th = g.uniform(0.0, 2.0 * np.pi, m)
+            t = (1.0 - np.exp(1j * th)) / nrm2
+        else:
+            t = 2.0 / nrm2
+            t[LL[a:e] == 1] = 0.0
+        hh[a:e] = v
+        tau[a:e] = t
+    return hh.reshape(-1), tau
+
+
+def gaussian_block(n, nev, complex_=False, seed=0):
+    """Dense n x nev column-major block, entries N(0, 1/n) (complex: each part
+    N(0, 1/(2n))), the size of unit eigenvector entries."""
+    g = _rng(seed)
+    s = 1.0 / np.sqrt(n)
+    if complex_:
+        h = s * np.sqrt(0.5)
+        Z = g.standard_normal((nev, n)) * h + 1j * (g.standard_normal((nev, n)) * h)
+    else:
+        Z = g.standard_normal((nev, n)) * s
+    return Z.T  # F-ordered view: column c is contiguous
+
+
+def to_dtype(x, name):
+    """Round fp64 / complex128 inputs to the request precision."""
+    return {"r64": np.float64, "r32": np.float32, "c64": np.complex128}[name](x) \
+        if np.isscalar(x) else x.astype(
+            {"r64": np.float64, "r32": np.float32, "c64": np.complex128}[name])
+
+
+def batched_sizes(count=256, lo=200, hi=2000, seed=401):
+    """Problem sizes of the batched workload: n_i ~ U{lo..hi}."""
+    return _rng(seed).integers(lo, hi + 1, size=count)
+
+
+def scf_sequence_sizes(count=64, lo=1000, hi=6000, seed=501):
+    """Per-sequence sizes of the served SCF stream: n_q ~ U{lo..hi}."""
+    return _rng(seed).integers(lo, hi + 1, size=count)
