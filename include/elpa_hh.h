@@ -1,0 +1,130 @@
+/*
+ * elpa_hh.h -- C ABI of the MI355X (gfx950) back-transformation of
+ * eigenvectors from tridiagonal to band form, the hot step of the two-stage
+ * Hermitian eigensolver.
+ *
+ * Operation (Kus et al., "Optimizations of the Eigensolvers in the ELPA
+ * Library", Sec. 2: the back-transformation V~ = Q^H V^ that follows the
+ * tridiagonal solve of Eq. Esolv, applied in the two-stage method to the
+ * band -> tridiagonal reflectors; Sec. 3.1 names this part of the
+ * back-transformation as the compute-heavy kernel that BLAS cannot express):
+ *
+ *     Q <- H(0,0) H(0,1) ... H(n-2, J(n-2)-1) Q,     H(s,j) = I - tau v v^H
+ *
+ * for every reflector of the one-column-per-step bulge chase: sweep
+ * s = 0..n-2, chase step j = 0..J(s)-1 with J(s) = ceil((n-1-s)/nbw), acting
+ * on rows [r, r+L), r = s+1+j*nbw, L = min(nbw, n-r).  The last generated
+ * reflector is applied first.  H (not H^H) is applied; the paper's Q_i is
+ * our H^H, its beta_i our conj(tau).
+ *
+ * Layouts (all device memory unless stated otherwise):
+ *   Q    n x nev, column major, element (i, c) at Q[i + c*ldq], ldq >= n,
+ *        overwritten in place.  Complex values are interleaved (re, im).
+ *   hh   reflector vectors, slot-major in generation order (s ascending,
+ *        then j ascending): slot k occupies hh[k*nbw .. k*nbw+nbw-1] with
+ *        hh[k*nbw] = 1, then v[1..L-1], then zeros up to nbw.
+ *        Slot offsets follow from (n, nbw) alone (see
+ *        elpa_hh_num_reflectors / elpa_hh_slot_offset).
+ *   tau  one scalar per slot, same element type as Q; tau = 0 is identity.
+ *
+ * Element types: ELPA_R64 (double), ELPA_R32 (float), ELPA_C64 (complex
+ * double, 16-byte elements).  hh, tau and Q share the element type.
+ *
+ * Ownership and asynchrony: the caller owns every buffer.  Calls are
+ * asynchronous on `stream` (a hipStream_t; NULL = the null stream) and keep
+ * no pointer after returning; buffers must stay valid until the stream has
+ * executed the work.  Calls on different streams are independent and
+ * thread-safe.
+ *
+ * Errors: every argument is validated before anything is enqueued; on an
+ * error nothing is enqueued and Q is untouched.  n <= 1 or nev == 0 is a
+ * valid no-op (returns ELPA_OK without touching any pointer).
+ */
+#ifndef ELPA_HH_H
+#define ELPA_HH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element types */
+enum { ELPA_R64 = 0, ELPA_R32 = 1, ELPA_C64 = 2 };
+
+/* return codes */
+enum {
+    ELPA_OK = 0,
+    ELPA_ERR_ARG = -1,    /* bad size, ldq < n, nbw < 1, null pointer */
+    ELPA_ERR_DTYPE = -2,  /* unknown element type */
+    ELPA_ERR_ALIGN = -3,  /* pointer not aligned to the element size */
+    ELPA_ERR_NOMEM = -4,  /* device workspace could not be allocated */
+    ELPA_ERR_DEVICE = -5, /* HIP launch or runtime failure */
+    ELPA_ERR_PLAN = -6    /* explicit plan not valid for this problem */
+};
+
+/* kernel family selection */
+enum {
+    ELPA_PATH_AUTO = 0,   /* library choice */
+    ELPA_PATH_REF = 1,    /* one reflector at a time, any nbw */
+    ELPA_PATH_STRIPE = 2  /* register-window stripe kernel, k sweeps fused */
+};
+
+/*
+ * Explicit execution plan (tests, autotuning).  Zero fields mean "library
+ * default".  path: ELPA_PATH_*; k: sweeps fused per pass (the stripe kernel
+ * keeps an (nbw + k - 1)-row window per column in registers).
+ */
+typedef struct {
+    int32_t path;
+    int32_t k;
+    int32_t reserved0;
+    int32_t reserved1;
+} elpa_hh_plan;
+
+/*
+ * Number of reflector slots N_refl = sum_s J(s) of an n x n band matrix of
+ * semi-bandwidth nbw (the length of tau; hh holds N_refl*nbw elements).
+ * Returns 0 for n <= 1 and -1 for nbw < 1 or n < 0.
+ */
+int64_t elpa_hh_num_reflectors(int64_t n, int64_t nbw);
+
+/*
+ * Slot index of the first reflector of sweep s (sum of J(s') for s' < s),
+ * 0 <= s <= n-1 (s = n-1 gives N_refl).  Returns -1 on bad arguments.
+ */
+int64_t elpa_hh_slot_offset(int64_t n, int64_t nbw, int64_t s);
+
+/*
+ * Q <- H(0,0) ... H(n-2, J-1) Q as described above, with the library's plan.
+ * hh, tau, Q: device pointers; stream: hipStream_t or NULL.
+ */
+int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void *hh,
+                  const void *tau, void *Q, int64_t ldq, int32_t dtype,
+                  void *stream);
+
+/*
+ * Same operation with an explicit plan (host pointer, may be NULL = auto).
+ * ELPA_ERR_PLAN if the plan cannot run this problem (e.g. a stripe kernel
+ * that is not built for this nbw / k / dtype).
+ */
+int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void *hh,
+                       const void *tau, void *Q, int64_t ldq, int32_t dtype,
+                       void *stream, const elpa_hh_plan *plan);
+
+/*
+ * Whether an explicit plan can run (n, nbw, dtype): 1 yes, 0 no.
+ */
+int elpa_hh_plan_supported(int64_t nbw, int32_t dtype, const elpa_hh_plan *plan);
+
+/* Static message for a return code (never NULL). */
+const char *elpa_strerror(int code);
+
+/* Library version string (never NULL). */
+const char *elpa_hh_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ELPA_HH_H */

@@ -1,0 +1,14 @@
+"""MI355X (gfx950) back-transformation of eigenvectors from tridiagonal to
+band form: the hot step of the two-stage Hermitian eigensolver (Kus et al.,
+"Optimizations of the Eigensolvers in the ELPA Library", Sec. 2 and 3.1).
+
+Thin ctypes binding of the C ABI in include/elpa_hh.h.  Every step of the
+computation runs in the HIP library libelpahip.so; this module only
+marshals torch tensors (device memory, streams) into pointers and sizes.
+There is no CPU fallback: if the library is missing, import of the binding
+functions raises.
+"""
+from .binding import (  # noqa: F401
+    C64, R32, R64, PATH_AUTO, PATH_REF, PATH_STRIPE, ElpaError, hh_trafo, hh_trafo_ptr,
+    library, library_path, num_reflectors, plan_supported, slot_offset, strerror, version,
+)

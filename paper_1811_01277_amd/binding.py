@@ -1,0 +1,136 @@
+"""ctypes marshalling for libelpahip.so (argument conversion only)."""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_NAME = "libelpahip.so"
+
+R64, R32, C64 = 0, 1, 2
+PATH_AUTO, PATH_REF, PATH_STRIPE = 0, 1, 2
+
+_lib = None
+
+
+class ElpaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("elpa_hh error %d: %s" % (code, msg))
+        self.code = code
+
+
+class _Plan(C.Structure):
+    _fields_ = [("path", C.c_int32), ("k", C.c_int32), ("reserved0", C.c_int32),
+                ("reserved1", C.c_int32)]
+
+
+def library_path():
+    return os.path.join(HERE, _LIB_NAME)
+
+
+def library():
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise ImportError("%s not built; run paper_1811_01277_amd/build.py" % path)
+        L = C.CDLL(path)
+        i64, i32, p = C.c_int64, C.c_int32, C.c_void_p
+        L.elpa_hh_num_reflectors.argtypes = [i64, i64]
+        L.elpa_hh_num_reflectors.restype = i64
+        L.elpa_hh_slot_offset.argtypes = [i64, i64, i64]
+        L.elpa_hh_slot_offset.restype = i64
+        L.elpa_hh_trafo.argtypes = [i64, i64, i64, p, p, p, i64, i32, p]
+        L.elpa_hh_trafo.restype = C.c_int
+        L.elpa_hh_trafo_plan.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, C.POINTER(_Plan)]
+        L.elpa_hh_trafo_plan.restype = C.c_int
+        L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
+        L.elpa_hh_plan_supported.restype = C.c_int
+        L.elpa_strerror.argtypes = [C.c_int]
+        L.elpa_strerror.restype = C.c_char_p
+        L.elpa_hh_version.argtypes = []
+        L.elpa_hh_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def strerror(code):
+    return library().elpa_strerror(code).decode()
+
+
+def version():
+    return library().elpa_hh_version().decode()
+
+
+def num_reflectors(n, nbw):
+    return int(library().elpa_hh_num_reflectors(n, nbw))
+
+
+def slot_offset(n, nbw, s):
+    return int(library().elpa_hh_slot_offset(n, nbw, s))
+
+
+def _plan(path, k):
+    if path is None and not k:
+        return None
+    return _Plan(int(path or 0), int(k or 0), 0, 0)
+
+
+def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
+    pl = _plan(path, k)
+    return bool(library().elpa_hh_plan_supported(nbw, dtype, C.byref(pl) if pl else None))
+
+
+def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0):
+    """Raw-pointer entry: returns the library's status code (no raise)."""
+    pl = _plan(path, k)
+    return int(library().elpa_hh_trafo_plan(
+        n, nev, nbw, C.c_void_p(hh), C.c_void_p(tau), C.c_void_p(q), ldq, dtype,
+        C.c_void_p(stream), C.byref(pl) if pl is not None else None))
+
+
+def _dtype_code(t):
+    import torch
+    m = {torch.float64: R64, torch.float32: R32, torch.complex128: C64}
+    if t.dtype not in m:
+        raise TypeError("unsupported dtype %s" % t.dtype)
+    return m[t.dtype]
+
+
+def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0):
+    """Q <- H(0,0) ... H(n-2,J-1) Q in place on a column-major torch tensor.
+
+    q:   (n, nev) device tensor with q.stride(0) == 1 (column major, ldq =
+         q.stride(1)); float64, float32 or complex128.
+    hh:  1-D contiguous tensor of N_refl*nbw reflector entries (same dtype).
+    tau: 1-D contiguous tensor of N_refl scalars (same dtype).
+    stream: torch.cuda.Stream or raw hipStream_t int; default: current stream.
+    """
+    import torch
+    if q.dim() != 2:
+        raise ValueError("q must be 2-D (n, nev)")
+    n, nev = q.shape
+    if n > 1 and nev > 0 and q.stride(0) != 1:
+        raise ValueError("q must be column major (stride(0) == 1)")
+    ldq = q.stride(1) if nev > 1 else max(n, 1)
+    dt = _dtype_code(q)
+    if hh.dtype != q.dtype or tau.dtype != q.dtype:
+        raise TypeError("hh, tau and q must share a dtype")
+    if not (hh.is_contiguous() and tau.is_contiguous()):
+        raise ValueError("hh and tau must be contiguous")
+    nr = num_reflectors(n, nbw) if n > 1 else 0
+    if nr > 0 and (hh.numel() < nr * nbw or tau.numel() < nr):
+        raise ValueError("hh needs %d and tau %d elements" % (nr * nbw, nr))
+    for t in (q, hh, tau):
+        if n > 1 and nev > 0 and not t.is_cuda:
+            raise ValueError("q, hh and tau must be device tensors")
+    if stream is None:
+        st = torch.cuda.current_stream(q.device).cuda_stream if q.is_cuda else 0
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = stream.cuda_stream
+    rc = hh_trafo_ptr(n, nev, nbw, hh.data_ptr(), tau.data_ptr(), q.data_ptr(), ldq, dt, st,
+                      path, k)
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    return q

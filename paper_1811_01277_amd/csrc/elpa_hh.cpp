@@ -1,0 +1,145 @@
+// C ABI of the tridiagonal->band back-transformation (declared in
+// include/elpa_hh.h): argument validation, plan selection and launch.
+#include "../../include/elpa_hh.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "hh_common.h"
+#include "hh_dispatch.h"
+
+namespace {
+
+int64_t elem_size(int32_t dtype) {
+  switch (dtype) {
+    case ELPA_R64: return 8;
+    case ELPA_R32: return 4;
+    case ELPA_C64: return 16;
+    default: return 0;
+  }
+}
+
+const ehh::StripeEntry* find_stripe(int32_t dtype, int64_t nb, int k) {
+  int cnt = 0;
+  const ehh::StripeEntry* tab = ehh::stripe_table(&cnt);
+  for (int i = 0; i < cnt; ++i) {
+    const ehh::StripeEntry& e = tab[i];
+    if (e.dtype == dtype && e.nb == nb && e.k == k) return &e;
+  }
+  return nullptr;
+}
+
+// Default number of fused sweeps per pass for the stripe kernel.
+int default_k(int32_t dtype, int64_t nb) {
+  const int pref[] = {16, 8, 6, 4, 2, 1};
+  const int prefc[] = {2, 1};
+  if (dtype == ELPA_C64) {
+    for (int k : prefc)
+      if (find_stripe(dtype, nb, k)) return k;
+    return 0;
+  }
+  for (int k : pref)
+    if (find_stripe(dtype, nb, k)) return k;
+  return 0;
+}
+
+bool aligned(const void* p, int64_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+int validate(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau, void* Q,
+             int64_t ldq, int32_t dtype) {
+  if (n < 0 || nev < 0 || nbw < 1) return ELPA_ERR_ARG;
+  const int64_t es = elem_size(dtype);
+  if (es == 0) return ELPA_ERR_DTYPE;
+  if (n <= 1 || nev == 0) return ELPA_OK;
+  if (ldq < n) return ELPA_ERR_ARG;
+  if (!hh || !tau || !Q) return ELPA_ERR_ARG;
+  // byte offsets ldq*(nev-1)+n and N_refl*nbw must fit in int64
+  if (nev > 1 && ldq > (INT64_MAX / es - n) / (nev - 1)) return ELPA_ERR_ARG;
+  const int64_t nr = ehh::csum(n - 1, nbw);
+  if (nr > INT64_MAX / nbw / es) return ELPA_ERR_ARG;
+  if (!aligned(hh, es) || !aligned(tau, es) || !aligned(Q, es)) return ELPA_ERR_ALIGN;
+  return ELPA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t elpa_hh_num_reflectors(int64_t n, int64_t nbw) {
+  if (n < 0 || nbw < 1) return -1;
+  if (n <= 1) return 0;
+  return ehh::csum(n - 1, nbw);
+}
+
+int64_t elpa_hh_slot_offset(int64_t n, int64_t nbw, int64_t s) {
+  if (n < 1 || nbw < 1 || s < 0 || s > n - 1) return -1;
+  return ehh::slot_offset(n, nbw, s);
+}
+
+int elpa_hh_plan_supported(int64_t nbw, int32_t dtype, const elpa_hh_plan* plan) {
+  if (elem_size(dtype) == 0 || nbw < 1) return 0;
+  const int path = plan ? plan->path : ELPA_PATH_AUTO;
+  switch (path) {
+    case ELPA_PATH_AUTO:
+    case ELPA_PATH_REF: return 1;
+    case ELPA_PATH_STRIPE: {
+      const int k = (plan && plan->k > 0) ? plan->k : default_k(dtype, nbw);
+      return (k > 0 && find_stripe(dtype, nbw, k)) ? 1 : 0;
+    }
+    default: return 0;
+  }
+}
+
+int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau,
+                       void* Q, int64_t ldq, int32_t dtype, void* stream,
+                       const elpa_hh_plan* plan) {
+  int rc = validate(n, nev, nbw, hh, tau, Q, ldq, dtype);
+  if (rc != ELPA_OK) return rc;
+  if (n <= 1 || nev == 0) return ELPA_OK;
+  if (plan && plan->path != ELPA_PATH_AUTO && plan->path != ELPA_PATH_REF &&
+      plan->path != ELPA_PATH_STRIPE)
+    return ELPA_ERR_PLAN;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int path = plan ? plan->path : ELPA_PATH_AUTO;
+  int k = (plan && plan->k > 0) ? plan->k : 0;
+  const ehh::StripeEntry* se = nullptr;
+  if (path == ELPA_PATH_AUTO) {
+    const int kd = k ? k : default_k(dtype, nbw);
+    se = kd ? find_stripe(dtype, nbw, kd) : nullptr;
+    path = se ? ELPA_PATH_STRIPE : ELPA_PATH_REF;
+  } else if (path == ELPA_PATH_STRIPE) {
+    const int kd = k ? k : default_k(dtype, nbw);
+    se = kd ? find_stripe(dtype, nbw, kd) : nullptr;
+    if (!se) return ELPA_ERR_PLAN;
+  }
+  hipError_t err;
+  if (path == ELPA_PATH_STRIPE) {
+    err = se->fn(hh, tau, Q, ldq, n, nev, st);
+  } else {
+    err = ehh::ref_launcher(dtype)(hh, tau, Q, ldq, n, nev, nbw, st);
+  }
+  return err == hipSuccess ? ELPA_OK : ELPA_ERR_DEVICE;
+}
+
+int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau, void* Q,
+                  int64_t ldq, int32_t dtype, void* stream) {
+  return elpa_hh_trafo_plan(n, nev, nbw, hh, tau, Q, ldq, dtype, stream, nullptr);
+}
+
+const char* elpa_strerror(int code) {
+  switch (code) {
+    case ELPA_OK: return "success";
+    case ELPA_ERR_ARG: return "invalid argument (size, leading dimension, nbw or null pointer)";
+    case ELPA_ERR_DTYPE: return "unknown element type";
+    case ELPA_ERR_ALIGN: return "pointer not aligned to the element size";
+    case ELPA_ERR_NOMEM: return "device workspace allocation failed";
+    case ELPA_ERR_DEVICE: return "HIP launch or runtime failure";
+    case ELPA_ERR_PLAN: return "explicit plan cannot run this problem";
+    default: return "unknown error code";
+  }
+}
+
+const char* elpa_hh_version(void) { return "elpa-hip 0.1 (gfx950)"; }
+
+}  // extern "C"

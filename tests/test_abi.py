@@ -1,0 +1,113 @@
+"""Host-side tests of the C ABI (no GPU needed, no compute call is made).
+
+* The library loads and exports every function include/elpa_hh.h declares.
+* Slot arithmetic equals a brute-force enumeration.
+* Every invalid argument returns its error code before anything is enqueued
+  (checked with host buffers that must stay untouched), n <= 1 and nev == 0
+  are no-ops.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1811_01277_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "elpa_hh.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(elpa_\w+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = P.library()
+    names = header_functions()
+    assert "elpa_hh_trafo" in names and len(names) >= 7
+    for nm in names:
+        assert hasattr(lib, nm), nm
+    out = subprocess.run(["nm", "-D", "--defined-only", P.library_path()],
+                         capture_output=True, text=True, check=True).stdout
+    exported = set(re.findall(r" T (elpa_\w+)", out))
+    assert set(names) <= exported
+
+
+@pytest.mark.parametrize("n,b", [(0, 1), (1, 4), (2, 1), (3, 2), (17, 4), (64, 64), (65, 64),
+                                 (512, 32), (8192, 64), (1000, 7)])
+def test_slot_arithmetic_brute_force(n, b):
+    J = [-(-(n - 1 - s) // b) for s in range(max(n - 1, 0))]
+    assert P.num_reflectors(n, b) == sum(J)
+    acc = 0
+    for s in range(max(n - 1, 0)):
+        assert P.slot_offset(n, b, s) == acc
+        acc += J[s]
+    if n >= 1:
+        assert P.slot_offset(n, b, n - 1) == acc
+
+
+def test_slot_arithmetic_large():
+    assert P.num_reflectors(20000, 64) == 3134695
+    assert P.num_reflectors(8192, 64) == 528256
+    assert P.num_reflectors(2000, 32) == 63441
+    assert P.num_reflectors(5, 0) == -1
+
+
+def _buf(nbytes, fill=7):
+    a = np.full(nbytes, fill, dtype=np.uint8)
+    return a, a.ctypes.data
+
+
+def test_error_codes_and_untouched_buffers():
+    q, qp = _buf(4096)
+    h, hp = _buf(4096)
+    t, tp = _buf(512)
+    snap = q.copy()
+    E = {"arg": -1, "dtype": -2, "align": -3}
+    cases = [
+        (dict(n=10, nev=5, nbw=0), E["arg"]),          # nbw < 1
+        (dict(n=-1, nev=5, nbw=2), E["arg"]),          # n < 0
+        (dict(n=10, nev=-1, nbw=2), E["arg"]),         # nev < 0
+        (dict(n=10, nev=5, nbw=2, ldq=9), E["arg"]),   # ldq < n
+        (dict(n=10, nev=5, nbw=2, dtype=7), E["dtype"]),
+        (dict(n=10, nev=5, nbw=2, dtype=-1), E["dtype"]),
+        (dict(n=10, nev=5, nbw=2, q=0), E["arg"]),     # null pointers
+        (dict(n=10, nev=5, nbw=2, hh=0), E["arg"]),
+        (dict(n=10, nev=5, nbw=2, tau=0), E["arg"]),
+        (dict(n=10, nev=5, nbw=2, q=qp + 4), E["align"]),
+        (dict(n=10, nev=5, nbw=2, hh=hp + 8, dtype=2), E["align"]),
+        (dict(n=10, nev=5, nbw=2, tau=tp + 2, dtype=1), E["align"]),
+        (dict(n=10, nev=5, nbw=2, path=9), -6),        # unknown plan path
+        (dict(n=10, nev=5, nbw=5, path=2, k=3), -6),   # stripe not built for nbw=5
+        (dict(n=10, nev=2, nbw=2, ldq=2 ** 62), E["arg"]),  # address overflow
+    ]
+    for kw, want in cases:
+        a = dict(n=10, nev=5, nbw=2, hh=hp, tau=tp, q=qp, ldq=None, dtype=0, path=None, k=0)
+        a.update(kw)
+        ldq = a["n"] if a["ldq"] is None else a["ldq"]
+        rc = P.hh_trafo_ptr(a["n"], a["nev"], a["nbw"], a["hh"], a["tau"], a["q"], ldq,
+                            a["dtype"], 0, a["path"], a["k"])
+        assert rc == want, (kw, rc)
+        assert P.strerror(rc) and P.strerror(rc) != "unknown error code"
+    assert np.array_equal(q, snap)
+
+
+def test_noops_touch_nothing():
+    # n <= 1 or nev == 0: success without dereferencing anything (null pointers)
+    assert P.hh_trafo_ptr(1, 5, 3, 0, 0, 0, 1, 0) == 0
+    assert P.hh_trafo_ptr(0, 5, 3, 0, 0, 0, 1, 0) == 0
+    assert P.hh_trafo_ptr(10, 0, 3, 0, 0, 0, 10, 0) == 0
+
+
+def test_plan_support_table():
+    assert P.plan_supported(64, P.R64, P.PATH_STRIPE, 16)
+    assert P.plan_supported(32, P.R32, P.PATH_STRIPE, 32)
+    assert P.plan_supported(5, P.R64, P.PATH_REF)
+    assert P.plan_supported(5, P.R64, P.PATH_AUTO)
+    assert not P.plan_supported(5, P.R64, P.PATH_STRIPE, 4)
+    assert not P.plan_supported(64, 9, P.PATH_AUTO)
+    assert P.strerror(12345) == "unknown error code"

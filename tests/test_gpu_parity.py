@@ -1,0 +1,206 @@
+"""GPU parity of elpa_hh_trafo (through the C ABI) against the CPU oracle.
+
+Bar (max-abs error divided by max |Q_ref|): 1e-12 for real and complex fp64,
+5e-5 for fp32.  fp32 inputs are the fp64 inputs rounded to fp32; the oracle
+applies those rounded values in fp64, so the measured error is the kernel's
+fp32 arithmetic alone.  The fp32 error against the unrounded fp64 oracle is
+printed beside it.
+
+Small sizes compare every element and span several 64-column stripes and a
+ragged column / row tail; the full sizes (n = 8192 and 20000) compare sampled
+columns, which the oracle computes one by one.
+"""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import bt, checks, solve
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
+KS = [1, 2, 4, 6, 8, 16, 32]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_01277_amd as P
+    P.library()
+    return torch, torch.device("cuda:0")
+
+
+def tdtype(torch, dt):
+    return {"r64": torch.float64, "r32": torch.float32, "c64": torch.complex128}[dt]
+
+
+def npdtype(dt):
+    return {"r64": np.float64, "r32": np.float32, "c64": np.complex128}[dt]
+
+
+def upload_q(torch, dev, Z, dt, ldq=None):
+    """Column-major (n, nev) device tensor, optionally with padding rows."""
+    n, nev = Z.shape
+    ldq = n if ldq is None else ldq
+    buf = torch.zeros((nev, ldq), dtype=tdtype(torch, dt))
+    buf[:, :n] = torch.from_numpy(np.ascontiguousarray(Z.T).astype(npdtype(dt)))
+    buf = buf.to(dev)
+    return buf, buf[:, :n].t()
+
+
+def run_gpu(torch, dev, hh, tau, Z, nbw, dt, path=None, k=0, ldq=None):
+    import paper_1811_01277_amd as P
+    buf, q = upload_q(torch, dev, Z, dt, ldq)
+    h = torch.from_numpy(hh.astype(npdtype(dt))).to(dev)
+    t = torch.from_numpy(tau.astype(npdtype(dt))).to(dev)
+    P.hh_trafo(q, h, t, nbw, path=path, k=k)
+    torch.cuda.synchronize()
+    return buf.cpu().numpy().T  # (ldq, nev)
+
+
+def oracle_inputs(n, nbw, nev, dt, seed, real_pipeline=False):
+    cplx = dt == "c64"
+    if real_pipeline:
+        A = W.herm_gaussian(n, seed) if cplx else W.sym_gaussian(n, seed)
+        r = solve.solve_two_stage(A, nbw, nev)
+        hh, tau = r["hh"], r["tau"]
+        Z = r["Zt"].astype(np.complex128 if cplx else np.float64)
+    else:
+        hh, tau = W.synthetic_reflectors(n, nbw, complex_=cplx, seed=seed)
+        Z = np.asfortranarray(W.gaussian_block(n, nev, complex_=cplx, seed=seed + 1))
+    return hh, tau, Z
+
+
+def rounded(x, dt):
+    """The values the kernel receives, back in fp64 for the oracle."""
+    if dt == "r32":
+        return x.astype(np.float32).astype(np.float64)
+    return x
+
+
+def plans(nbw, dt):
+    import paper_1811_01277_amd as P
+    code = {"r64": P.R64, "r32": P.R32, "c64": P.C64}[dt]
+    out = [(None, 0), (P.PATH_REF, 0)]
+    out += [(P.PATH_STRIPE, k) for k in KS if P.plan_supported(nbw, code, P.PATH_STRIPE, k)]
+    return out
+
+
+SMALL = [
+    # (n, nbw, nev, seed, real pipeline)
+    (512, 32, 512, 101, True),    # the first workload: full oracle pipeline
+    (97, 32, 70, 11, False),      # ragged rows and one partial stripe
+    (130, 64, 129, 12, False),    # 3 stripes, last with one column
+    (300, 64, 65, 13, True),
+    (65, 64, 64, 14, False),      # one chase step per sweep except the first
+    (64, 64, 3, 15, False),       # nbw >= n-1
+    (2, 32, 1, 16, False),        # a single reflector
+    (3, 1, 5, 17, False),         # nbw = 1 (generic path)
+    (200, 7, 33, 18, True),       # nbw without a stripe kernel
+]
+
+
+@pytest.mark.parametrize("dt", ["r64", "r32", "c64"])
+@pytest.mark.parametrize("case", SMALL, ids=[f"n{c[0]}_b{c[1]}_e{c[2]}" for c in SMALL])
+def test_parity_small_all_plans(torch_dev, case, dt):
+    torch, dev = torch_dev
+    n, nbw, nev, seed, real = case
+    hh, tau, Z = oracle_inputs(n, nbw, nev, dt, seed, real)
+    ref = bt.bt_tridiag_to_band(rounded(hh, dt), rounded(tau, dt), rounded(Z, dt), n, nbw)
+    ref_unrounded = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw) if dt == "r32" else ref
+    for path, k in plans(nbw, dt):
+        print(f"case n={n} nbw={nbw} nev={nev} dt={dt} path={path} k={k}", flush=True)
+        got = run_gpu(torch, dev, hh, tau, Z, nbw, dt, path, k)[:n]
+        err = checks.max_rel_err(got, ref)
+        assert err <= TOL[dt], (path, k, err)
+        if dt == "r32":
+            print(f"  fp32 err vs fp64 oracle of unrounded inputs: "
+                  f"{checks.max_rel_err(got, ref_unrounded):.3e} (vs rounded: {err:.3e})")
+
+
+@pytest.mark.parametrize("dt", ["r64", "c64"])
+def test_padding_rows_untouched_and_replay_bitwise(torch_dev, dt):
+    torch, dev = torch_dev
+    n, nbw, nev, ldq = 150, 32, 100, 173
+    hh, tau, Z = oracle_inputs(n, nbw, nev, dt, 21)
+    ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
+    a = run_gpu(torch, dev, hh, tau, Z, nbw, dt, ldq=ldq)
+    b = run_gpu(torch, dev, hh, tau, Z, nbw, dt, ldq=ldq)
+    assert np.array_equal(a, b)
+    assert np.all(a[n:] == 0)
+    assert checks.max_rel_err(a[:n], ref) <= TOL[dt]
+
+
+def test_column_independence_nan_isolation_identity(torch_dev):
+    torch, dev = torch_dev
+    n, nbw, nev = 260, 64, 140
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "r64", 31)
+    full = run_gpu(torch, dev, hh, tau, Z, nbw, "r64")
+    sub = run_gpu(torch, dev, hh, tau, np.asfortranarray(Z[:, 70:75]), nbw, "r64")
+    assert np.array_equal(sub, full[:, 70:75])
+    Zn = Z.copy()
+    Zn[100, 7] = np.nan
+    got = run_gpu(torch, dev, hh, tau, Zn, nbw, "r64")
+    keep = [c for c in range(nev) if c != 7]
+    assert np.array_equal(got[:, keep], full[:, keep])
+    assert np.isnan(got[:, 7]).any()
+    ident = run_gpu(torch, dev, hh, np.zeros_like(tau), Z, nbw, "r64")
+    assert np.array_equal(ident, Z)
+
+
+def test_error_leaves_q_untouched(torch_dev):
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 40, 8, 10
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "r64", 41)
+    buf, q = upload_q(torch, dev, Z, "r64")
+    h = torch.from_numpy(hh).to(dev)
+    t = torch.from_numpy(tau).to(dev)
+    before = buf.clone()
+    rc = P.hh_trafo_ptr(n, nev, nbw, h.data_ptr(), t.data_ptr(), q.data_ptr(), n - 1, P.R64)
+    assert rc == -1
+    rc = P.hh_trafo_ptr(n, nev, nbw, h.data_ptr(), t.data_ptr(), q.data_ptr() + 4, n, P.R64)
+    assert rc == -3
+    torch.cuda.synchronize()
+    assert torch.equal(buf, before)
+
+
+def sampled_columns(nev):
+    cols = {0, 1, 63, 64, nev // 2, nev - 1}
+    return sorted(c for c in cols if 0 <= c < nev)
+
+
+FULL = [
+    (8192, 64, 819, "r64"), (8192, 64, 4096, "r64"),
+    (20000, 64, 2000, "r64"), (20000, 64, 10000, "r64"), (20000, 64, 20000, "r64"),
+    (20000, 64, 2000, "r32"), (20000, 64, 2000, "c64"),
+]
+
+
+@pytest.mark.parametrize("case", FULL, ids=[f"n{c[0]}_e{c[2]}_{c[3]}" for c in FULL])
+def test_parity_full_size_sampled(torch_dev, case):
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev, dt = case
+    cplx = dt == "c64"
+    hh, tau = W.synthetic_reflectors(n, nbw, complex_=cplx, seed=n + nev)
+    Z = W.gaussian_block(n, nev, complex_=cplx, seed=n + nev + 1)
+    print(f"full case n={n} nev={nev} dt={dt}", flush=True)
+    q = torch.from_numpy(np.ascontiguousarray(Z.T).astype(npdtype(dt))).to(dev).t()
+    h = torch.from_numpy(hh.astype(npdtype(dt))).to(dev)
+    t = torch.from_numpy(tau.astype(npdtype(dt))).to(dev)
+    P.hh_trafo(q, h, t, nbw)
+    torch.cuda.synchronize()
+    cols = sampled_columns(nev)
+    got = q[:, cols].cpu().numpy()
+    ref = bt.bt_tridiag_to_band(rounded(hh, dt), rounded(tau, dt),
+                                rounded(np.asfortranarray(Z[:, cols]), dt), n, nbw)
+    err = checks.max_rel_err(got, ref)
+    print(f"  sampled max-abs rel err = {err:.3e}")
+    assert err <= TOL[dt]
+    # orthogonal reflectors preserve every column norm (all columns checked)
+    nq = torch.linalg.vector_norm(q.to(torch.complex128 if cplx else torch.float64), dim=0)
+    nz = torch.linalg.vector_norm(torch.from_numpy(Z.T.copy()).to(dev), dim=1)
+    rel = ((nq - nz).abs() / nz).max().item()
+    assert rel <= (1e-4 if dt == "r32" else 1e-11), rel
