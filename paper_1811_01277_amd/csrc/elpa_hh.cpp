@@ -32,8 +32,8 @@ const ehh::StripeEntry* find_stripe(int32_t dtype, int64_t nb, int k) {
 
 // Default number of fused sweeps per pass for the stripe kernel.
 int default_k(int32_t dtype, int64_t nb) {
-  const int pref[] = {16, 8, 6, 4, 2, 1};
-  const int prefc[] = {2, 1};
+  const int pref[] = {32, 16, 8, 4};
+  const int prefc[] = {4, 2};
   if (dtype == ELPA_C64) {
     for (int k : prefc)
       if (find_stripe(dtype, nb, k)) return k;
@@ -42,6 +42,22 @@ int default_k(int32_t dtype, int64_t nb) {
   for (int k : pref)
     if (find_stripe(dtype, nb, k)) return k;
   return 0;
+}
+
+// Compute-unit count of the current device (cached per device id).
+int device_cus() {
+  static int cache[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (dev < 0 || dev >= 64) dev = 0;
+  if (cache[dev] == 0) {
+    int cu = 0;
+    if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cu <= 0)
+      cu = 256;
+    cache[dev] = cu;
+  }
+  return cache[dev];
 }
 
 bool aligned(const void* p, int64_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -115,7 +131,7 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
   }
   hipError_t err;
   if (path == ELPA_PATH_STRIPE) {
-    err = se->fn(hh, tau, Q, ldq, n, nev, st);
+    err = se->fn(hh, tau, Q, ldq, n, nev, st, device_cus());
   } else {
     err = ehh::ref_launcher(dtype)(hh, tau, Q, ldq, n, nev, nbw, st);
   }

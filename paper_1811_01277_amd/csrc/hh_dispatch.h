@@ -7,7 +7,7 @@
 namespace ehh {
 
 using StripeLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
-                                    int64_t n, int64_t nev, hipStream_t st);
+                                    int64_t n, int64_t nev, hipStream_t st, int num_cu);
 using RefLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
                                  int64_t n, int64_t nev, int64_t nb, hipStream_t st);
 
@@ -15,6 +15,7 @@ struct StripeEntry {
   int dtype;
   int nb;
   int k;
+  int occ;  // waves per SIMD the kernel is compiled for
   StripeLaunch fn;
 };
 

@@ -19,7 +19,7 @@ from oracle import bt, checks, solve
 pytestmark = pytest.mark.gpu
 
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
-KS = [1, 2, 4, 6, 8, 16, 32]
+KS = [1, 2, 4, 6, 8, 16, 24, 32, 48, 64]
 
 
 @pytest.fixture(scope="module")
