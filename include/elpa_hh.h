@@ -73,13 +73,15 @@ enum {
 /*
  * Explicit execution plan (tests, autotuning).  Zero fields mean "library
  * default".  path: ELPA_PATH_*; k: sweeps fused per pass (the stripe kernel
- * keeps an (nbw + k - 1)-row window per column in registers).
+ * keeps an (nbw + k - 1)-row window per column in registers); steps: chase
+ * steps per tile of the stripe kernel's launch schedule (fewer steps: more
+ * tiles per launch, more launches).
  */
 typedef struct {
     int32_t path;
     int32_t k;
-    int32_t reserved0;
-    int32_t reserved1;
+    int32_t steps;
+    int32_t reserved;
 } elpa_hh_plan;
 
 /*
@@ -111,6 +113,34 @@ int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void *hh,
 int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void *hh,
                        const void *tau, void *Q, int64_t ldq, int32_t dtype,
                        void *stream, const elpa_hh_plan *plan);
+
+/*
+ * One problem of a batched call (host struct; the pointers are device
+ * pointers with the same meaning, layout and alignment rules as the
+ * arguments of elpa_hh_trafo).
+ */
+typedef struct {
+    int64_t n, nev, nbw, ldq;
+    const void *hh;
+    const void *tau;
+    void *Q;
+    int32_t dtype;
+    int32_t reserved;
+} elpa_hh_problem;
+
+/*
+ * Batched back-transformation: the same operation for every problem in
+ * probs[0..count) (host array, read before the call returns), asynchronous on
+ * `stream`.  Problems may differ in n, nev and ldq; problems that share
+ * (dtype, nbw) and have a compiled stripe kernel run together in one
+ * persistent launch (one launch per such group, in order on the stream), the
+ * others through the reference kernel one by one.  Every problem is validated
+ * first; if any is invalid nothing is enqueued and the code of the first
+ * invalid problem is returned.  The Q buffers of different problems must not
+ * overlap.  plan may be NULL (library choice) and applies to every group.
+ */
+int elpa_hh_trafo_batched(const elpa_hh_problem *probs, int64_t count, void *stream,
+                          const elpa_hh_plan *plan);
 
 /*
  * Whether an explicit plan can run (n, nbw, dtype): 1 yes, 0 no.

@@ -9,6 +9,6 @@ There is no CPU fallback: if the library is missing, import of the binding
 functions raises.
 """
 from .binding import (  # noqa: F401
-    C64, R32, R64, PATH_AUTO, PATH_REF, PATH_STRIPE, ElpaError, hh_trafo, hh_trafo_ptr,
+    C64, R32, R64, PATH_AUTO, PATH_REF, PATH_STRIPE, ElpaError, hh_trafo, hh_trafo_batched, hh_trafo_ptr,
     library, library_path, num_reflectors, plan_supported, slot_offset, strerror, version,
 )

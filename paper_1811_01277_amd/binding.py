@@ -18,8 +18,14 @@ class ElpaError(RuntimeError):
 
 
 class _Plan(C.Structure):
-    _fields_ = [("path", C.c_int32), ("k", C.c_int32), ("reserved0", C.c_int32),
-                ("reserved1", C.c_int32)]
+    _fields_ = [("path", C.c_int32), ("k", C.c_int32), ("steps", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nev", C.c_int64), ("nbw", C.c_int64), ("ldq", C.c_int64),
+                ("hh", C.c_void_p), ("tau", C.c_void_p), ("Q", C.c_void_p),
+                ("dtype", C.c_int32), ("reserved", C.c_int32)]
 
 
 def library_path():
@@ -43,6 +49,8 @@ def library():
         L.elpa_hh_trafo.restype = C.c_int
         L.elpa_hh_trafo_plan.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, C.POINTER(_Plan)]
         L.elpa_hh_trafo_plan.restype = C.c_int
+        L.elpa_hh_trafo_batched.argtypes = [C.POINTER(_Problem), i64, p, C.POINTER(_Plan)]
+        L.elpa_hh_trafo_batched.restype = C.c_int
         L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
         L.elpa_hh_plan_supported.restype = C.c_int
         L.elpa_strerror.argtypes = [C.c_int]
@@ -69,10 +77,10 @@ def slot_offset(n, nbw, s):
     return int(library().elpa_hh_slot_offset(n, nbw, s))
 
 
-def _plan(path, k):
-    if path is None and not k:
+def _plan(path, k, steps=0):
+    if path is None and not k and not steps:
         return None
-    return _Plan(int(path or 0), int(k or 0), 0, 0)
+    return _Plan(int(path or 0), int(k or 0), int(steps or 0), 0)
 
 
 def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
@@ -80,9 +88,9 @@ def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
     return bool(library().elpa_hh_plan_supported(nbw, dtype, C.byref(pl) if pl else None))
 
 
-def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0):
+def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0, steps=0):
     """Raw-pointer entry: returns the library's status code (no raise)."""
-    pl = _plan(path, k)
+    pl = _plan(path, k, steps)
     return int(library().elpa_hh_trafo_plan(
         n, nev, nbw, C.c_void_p(hh), C.c_void_p(tau), C.c_void_p(q), ldq, dtype,
         C.c_void_p(stream), C.byref(pl) if pl is not None else None))
@@ -96,7 +104,7 @@ def _dtype_code(t):
     return m[t.dtype]
 
 
-def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0):
+def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0):
     """Q <- H(0,0) ... H(n-2,J-1) Q in place on a column-major torch tensor.
 
     q:   (n, nev) device tensor with q.stride(0) == 1 (column major, ldq =
@@ -130,7 +138,43 @@ def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0):
     else:
         st = stream.cuda_stream
     rc = hh_trafo_ptr(n, nev, nbw, hh.data_ptr(), tau.data_ptr(), q.data_ptr(), ldq, dt, st,
-                      path, k)
+                      path, k, steps)
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
     return q
+
+
+def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0):
+    """Batched Q <- H ... H Q over a list of (q, hh, tau, nbw) tensor tuples.
+
+    Each q is a column-major (n, nev) device tensor as in hh_trafo; problems
+    may differ in n, nev and dtype.  One persistent launch per (dtype, nbw)
+    group on one stream.
+    """
+    import torch
+    arr = (_Problem * max(1, len(problems)))()
+    dev = None
+    for i, (q, hh, tau, nbw) in enumerate(problems):
+        n, nev = q.shape
+        if n > 1 and nev > 0 and q.stride(0) != 1:
+            raise ValueError("q must be column major (stride(0) == 1)")
+        if hh.dtype != q.dtype or tau.dtype != q.dtype:
+            raise TypeError("hh, tau and q must share a dtype")
+        nr = num_reflectors(n, nbw) if n > 1 else 0
+        if nr > 0 and (hh.numel() < nr * nbw or tau.numel() < nr):
+            raise ValueError("problem %d: hh needs %d and tau %d elements" % (i, nr * nbw, nr))
+        ldq = q.stride(1) if nev > 1 else max(n, 1)
+        arr[i] = _Problem(n, nev, nbw, ldq, hh.data_ptr(), tau.data_ptr(), q.data_ptr(),
+                          _dtype_code(q), 0)
+        dev = q.device if dev is None else dev
+    if stream is None:
+        st = torch.cuda.current_stream(dev).cuda_stream if dev is not None and dev.type == "cuda" else 0
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = stream.cuda_stream
+    pl = _plan(path, k, steps)
+    rc = int(library().elpa_hh_trafo_batched(arr, len(problems), C.c_void_p(st),
+                                              C.byref(pl) if pl is not None else None))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <utility>
+#include <vector>
 
 #include "hh_common.h"
 #include "hh_dispatch.h"
@@ -131,11 +134,57 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
   }
   hipError_t err;
   if (path == ELPA_PATH_STRIPE) {
-    err = se->fn(hh, tau, Q, ldq, n, nev, st, device_cus());
+    err = se->fn(hh, tau, Q, ldq, n, nev, plan ? plan->steps : 0, st, device_cus());
   } else {
     err = ehh::ref_launcher(dtype)(hh, tau, Q, ldq, n, nev, nbw, st);
   }
   return err == hipSuccess ? ELPA_OK : ELPA_ERR_DEVICE;
+}
+
+int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* stream,
+                          const elpa_hh_plan* plan) {
+  if (count < 0 || (count > 0 && !probs)) return ELPA_ERR_ARG;
+  if (plan && plan->path != ELPA_PATH_AUTO && plan->path != ELPA_PATH_REF &&
+      plan->path != ELPA_PATH_STRIPE)
+    return ELPA_ERR_PLAN;
+  for (int64_t i = 0; i < count; ++i) {
+    const elpa_hh_problem& p = probs[i];
+    const int rc = validate(p.n, p.nev, p.nbw, p.hh, p.tau, p.Q, p.ldq, p.dtype);
+    if (rc != ELPA_OK) return rc;
+  }
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const int path = plan ? plan->path : ELPA_PATH_AUTO;
+  const int kreq = (plan && plan->k > 0) ? plan->k : 0;
+  // group by (dtype, nbw); groups without a stripe kernel go one by one
+  std::map<std::pair<int32_t, int64_t>, std::vector<int64_t>> groups;
+  std::vector<int64_t> singles;
+  for (int64_t i = 0; i < count; ++i) {
+    const elpa_hh_problem& p = probs[i];
+    if (p.n <= 1 || p.nev == 0) continue;
+    const int k = kreq ? kreq : default_k(p.dtype, p.nbw);
+    const bool stripe = path != ELPA_PATH_REF && k > 0 && find_stripe(p.dtype, p.nbw, k);
+    if (path == ELPA_PATH_STRIPE && !stripe) return ELPA_ERR_PLAN;
+    if (stripe)
+      groups[{p.dtype, p.nbw}].push_back(i);
+    else
+      singles.push_back(i);
+  }
+  const int cus = count > 0 ? device_cus() : 0;
+  for (auto& kv : groups) {
+    const int k = kreq ? kreq : default_k(kv.first.first, kv.first.second);
+    const ehh::StripeEntry* se = find_stripe(kv.first.first, kv.first.second, k);
+    const hipError_t err =
+        se->batched(probs, kv.second.data(), (int64_t)kv.second.size(),
+                    plan ? plan->steps : 0, st, cus);
+    if (err != hipSuccess) return ELPA_ERR_DEVICE;
+  }
+  for (int64_t i : singles) {
+    const elpa_hh_problem& p = probs[i];
+    const hipError_t err =
+        ehh::ref_launcher(p.dtype)(p.hh, p.tau, p.Q, p.ldq, p.n, p.nev, p.nbw, st);
+    if (err != hipSuccess) return ELPA_ERR_DEVICE;
+  }
+  return ELPA_OK;
 }
 
 int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau, void* Q,

@@ -5,43 +5,49 @@
 // the two-stage solver's first back-transformation (Kus et al., Sec. 2; the
 // compute-heavy part of the back-transformation singled out in Sec. 3.1).
 //
-// Stripe path (the fast one)
-// --------------------------
-// 1. Q (column major) is copied into a row-major workspace Qt whose rows hold
-//    ldt = 64*G columns (G = ceil(nev/64) stripes) and which has zero rows
-//    past n, enough for the deepest window.  A wave64 lane owns one column,
-//    so a row of a 64-column stripe is one 512-byte coalesced access, and no
-//    load or store needs a bounds check.
-// 2. Work is split into tasks (stripe c, sweep block m): block m holds the K
-//    consecutive sweeps [mK, mK+K-1].  A task slides a window of W = NB+K-1
-//    rows of its stripe down the matrix, one chase step j = 0, 1, ... at a
-//    time; at each step it applies the K reflectors (s, j) of its block,
-//    largest s first, to the W rows held in VGPRs, writes the NB rows that
-//    are final for this block and reads NB new ones.  Reflector values are
-//    wave-uniform and come through scalar loads (SGPR operands of the FMAs).
-//    Per lane and step: 2*NB*K FMAs per 2*NB row transfers.
-// 3. Order.  Blocks of one stripe must run from the top (largest sweeps) down,
-//    but only row by row: two reflectors (a, j), (c, j') with a > c share rows
-//    only if a - c >= NB*(j'-j-1)+1, so block m at step j only needs block
-//    m+1 to have finished its step j.  Each task publishes, after every step,
-//    the row below which its stripe is final (release, agent scope); the task
-//    of the next block waits on that value (acquire) before loading rows.
-//    The result equals strict reverse generation order up to the rounding of
-//    the dot products.
-// 4. Scheduling.  A persistent grid takes tickets from an atomic counter in
-//    dependency order (blocks descending, then stripes), so the task a wave
-//    waits on always holds an earlier ticket and is running or done: no
-//    deadlock, and every wave exits when the tickets run out.  Each stripe
-//    has up to ~(n/NB) tasks in flight at once, which fills the chip even for
-//    small nev.
-// 5. Qt is copied back into Q.
+// Stripe path
+// -----------
+// 1. Q (column major) is copied into a stripe-major workspace Qs: each
+//    64-column stripe (G = ceil(nev/64) of them) is a contiguous row-major
+//    block with zero rows past n, enough for the deepest window.  A wave64
+//    lane owns one column, so a row of a stripe is one 512-byte coalesced
+//    access, the row stride is a compile-time constant, and no load or store
+//    needs a bounds check.
+// 2. Sweeps are grouped into blocks of K consecutive sweeps [mK, mK+K-1]
+//    (m = 0..M-1).  Block m slides a window of W = NB+K-1 rows of a stripe
+//    down the matrix, one chase step j at a time; at each step it applies the
+//    K reflectors (s, j) of the block, largest s first, to the window held in
+//    VGPRs, writes the NB rows that are final for the block and reads NB new
+//    ones (2*NB*K FMAs per lane per 2*NB row transfers).
+// 3. Order.  Two reflectors (a, j), (c, j') with a > c share rows only if
+//    a - c >= NB*(j'-j-1)+1, so blocks may run from the top (largest sweeps)
+//    down with chase steps ascending inside a block, and block m at step j
+//    only needs block m+1 to have finished its step j.  The result equals
+//    strict reverse generation order up to the rounding of the dot products.
+// 4. Schedule (no synchronisation inside a launch).  A tile is (stripe c,
+//    block m, group q of S consecutive chase steps).  Launch t runs every
+//    tile with (M-1-m) + q = t.  Block m's group q then runs after block
+//    m+1's group q (launch t-1), which covers every row it needs, and the
+//    tiles of one launch touch disjoint rows of a stripe: block m's group q
+//    ends at row s0+K-1+(q+1)*S*NB, block m+1's group q+1 starts at row
+//    s0+K+1+(q+1)*S*NB, block m-1's group q-1 ends at row s0-1+q*S*NB and
+//    block m's group q starts at s0+1+q*S*NB.  Kernel boundaries give all
+//    ordering and visibility; a tile that ends mid-block writes its K-1
+//    carried rows back and the next group reloads them.  Launch count is
+//    about M + ceil(J0/S); S trades launches and window reloads for
+//    parallelism (tiles per launch ~ G * min(M, J0/S)).
+// 5. Qs is copied back into Q.
+// 6. Batched form: launch t runs the tiles of launch t of every problem of
+//    the batch (one element type and NB per launch sequence).
 //
 // Reference path: any nbw, one reflector at a time, column-major in place.
 #include "hh_common.h"
 #include "hh_dispatch.h"
 #include "hh_dpp.h"
 
+#include <algorithm>
 #include <type_traits>
+#include <vector>
 
 namespace ehh {
 
@@ -74,6 +80,105 @@ __global__ __launch_bounds__(64) void k_ref(const E* __restrict__ hh, const E* _
   }
 }
 
+
+// Geometry of one problem of the stripe path (device copy used by the
+// batched kernels).
+struct ProblemDesc {
+  const void* hh;
+  const void* tau;
+  void* Q;
+  void* Qs;
+  int64_t n, nev, ldq, rows_pad;
+  int G, M, S;
+  int tile0;   // first 64x64 conversion tile of this problem (rows_pad/64 * G tiles)
+  int otile0;  // first conversion tile back (ceil(n/64) * G tiles)
+  int pad;
+};
+
+// One launch's share of one problem in the batched diagonal schedule:
+// blocks [m0, m0 + mcount) of problem p, every stripe; tiles [tile0,
+// tile0 + mcount*G) of the launch.
+struct DiagEntry {
+  int p;
+  int m0;
+  int mcount;
+  int tile0;
+};
+
+// index i with key(d[i]) <= key < key(d[i+1]) (d sorted by key)
+template <typename T, int T::*F>
+__device__ __forceinline__ int find_by(const T* __restrict__ d, int count, int key) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (d[mid].*F <= key)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename E>
+__device__ __forceinline__ void to_rows_tile(const E* __restrict__ Q, int64_t ldq, int64_t n,
+                                             int64_t nev, E* __restrict__ Qs, int64_t rows_pad,
+                                             int64_t rt, int64_t c, E (*tile)[65]) {
+  const int64_t r0 = rt * 64, c0 = c * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t r = r0 + tx, col = c0 + cc;
+    tile[cc][tx] = (r < n && col < nev) ? Q[r + col * ldq] : Ops<E>::zero();
+  }
+  __syncthreads();
+  E* __restrict__ dst = Qs + c * rows_pad * 64;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr;
+    if (r < rows_pad) dst[r * 64 + tx] = tile[tx][rr];
+  }
+}
+
+template <typename E>
+__device__ __forceinline__ void from_rows_tile(const E* __restrict__ Qs, int64_t rows_pad,
+                                               E* __restrict__ Q, int64_t ldq, int64_t n,
+                                               int64_t nev, int64_t rt, int64_t c,
+                                               E (*tile)[65]) {
+  const int64_t r0 = rt * 64, c0 = c * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  const E* __restrict__ src = Qs + c * rows_pad * 64;
+  for (int rr = ty; rr < 64; rr += 4) {
+    const int64_t r = r0 + rr;
+    if (r < n) tile[rr][tx] = src[r * 64 + tx];
+  }
+  __syncthreads();
+  for (int cc = ty; cc < 64; cc += 4) {
+    const int64_t r = r0 + tx, col = c0 + cc;
+    if (r < n && col < nev) Q[r + col * ldq] = tile[tx][cc];
+  }
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_to_rows_b(const ProblemDesc* __restrict__ d, int count) {
+  __shared__ E tile[64][65];
+  const int t = (int)blockIdx.x;
+  const int p = find_by<ProblemDesc, &ProblemDesc::tile0>(d, count, t);
+  const ProblemDesc& P = d[p];
+  const int local = t - P.tile0;
+  to_rows_tile<E>((const E*)P.Q, P.ldq, P.n, P.nev, (E*)P.Qs, P.rows_pad, local / P.G,
+                  local % P.G, tile);
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_from_rows_b(const ProblemDesc* __restrict__ d,
+                                                     int count) {
+  __shared__ E tile[64][65];
+  const int t = (int)blockIdx.x;
+  const int p = find_by<ProblemDesc, &ProblemDesc::otile0>(d, count, t);
+  const ProblemDesc& P = d[p];
+  const int local = t - P.otile0;
+  from_rows_tile<E>((const E*)P.Qs, P.rows_pad, (E*)P.Q, P.ldq, P.n, P.nev, local / P.G,
+                    local % P.G, tile);
+}
+
 // ---------------------------------------------------------------------------
 // Layout conversion between Q (column major, ldq) and the stripe-major
 // workspace Qs: stripe c (columns 64c..64c+63) is a contiguous rows_pad x 64
@@ -85,18 +190,7 @@ __global__ __launch_bounds__(256) void k_to_rows(const E* __restrict__ Q, int64_
                                                  int64_t nev, E* __restrict__ Qs,
                                                  int64_t rows_pad) {
   __shared__ E tile[64][65];
-  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t r = r0 + tx, c = c0 + cc;
-    tile[cc][tx] = (r < n && c < nev) ? Q[r + c * ldq] : Ops<E>::zero();
-  }
-  __syncthreads();
-  E* __restrict__ dst = Qs + (int64_t)blockIdx.y * rows_pad * 64;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr;
-    if (r < rows_pad) dst[r * 64 + tx] = tile[tx][rr];
-  }
+  to_rows_tile<E>(Q, ldq, n, nev, Qs, rows_pad, blockIdx.x, blockIdx.y, tile);
 }
 
 template <typename E>
@@ -104,42 +198,12 @@ __global__ __launch_bounds__(256) void k_from_rows(const E* __restrict__ Qs, int
                                                    E* __restrict__ Q, int64_t ldq, int64_t n,
                                                    int64_t nev) {
   __shared__ E tile[64][65];
-  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const E* __restrict__ src = Qs + (int64_t)blockIdx.y * rows_pad * 64;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr;
-    if (r < n) tile[rr][tx] = src[r * 64 + tx];
-  }
-  __syncthreads();
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t r = r0 + tx, c = c0 + cc;
-    if (r < n && c < nev) Q[r + c * ldq] = tile[tx][cc];
-  }
-}
-
-__global__ void k_zero_i32(int* __restrict__ p, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0;
+  from_rows_tile<E>(Qs, rows_pad, Q, ldq, n, nev, blockIdx.x, blockIdx.y, tile);
 }
 
 // ---------------------------------------------------------------------------
-// Wavefront stripe kernel.
-//   Qs      stripe-major workspace, row r of stripe c at Qs + (c*rows_pad + r)*64
-//   prog    G*M ints (zeroed): prog[c*M + m] = rows final after task (c, m)
-//   ticket  one int (zeroed)
+// Reflector streaming helpers.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int wave_ticket(int* ticket) {
-  int t = 0;
-  if (threadIdx.x == 0) t = atomicAdd(ticket, 1);
-  return __builtin_amdgcn_readfirstlane(t);
-}
-
-__device__ __forceinline__ int load_progress(const int* p) {
-  return __builtin_amdgcn_readfirstlane(
-      __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-}
-
 // Reflector values travel through SGPRs in chunks of CH elements, with a
 // software pipeline of one chunk: the scalar loads of chunk q+1 are issued
 // right after the first FMA of chunk q and consumed by chunk q+1.  LLVM may
@@ -241,90 +305,6 @@ struct RevFor<0> {
   static __device__ __forceinline__ void run(F&&) {}
 };
 
-template <typename E, int NB, int K, int OCC>
-__global__ __launch_bounds__(64, OCC) void k_wave(const E* __restrict__ hh,
-                                                const E* __restrict__ hh2,
-                                                const E* __restrict__ tau, E* __restrict__ Qs,
-                                                int64_t rows_pad, int64_t n, int G, int M,
-                                                int* __restrict__ prog, int* ticket) {
-  using O = Ops<E>;
-  constexpr int W = NB + K - 1;
-  const int lane = threadIdx.x;
-  const int64_t ctot = csum(n - 1, NB);
-  const int ntask = G * M;
-  E x[W];
-  for (;;) {
-    const int tk = wave_ticket(ticket);
-    if (tk >= ntask) break;
-    const int m = M - 1 - tk / G;
-    const int c = tk - (tk / G) * G;
-    // uniform base of the stripe; row r of the lane's column is bp[r*64 + lane]
-    E* __restrict__ bp = Qs + (int64_t)c * rows_pad * 64;
-    const int64_t s0 = (int64_t)m * K;
-    const int64_t s1 = (s0 + K - 1 < n - 2) ? s0 + K - 1 : n - 2;
-    const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
-    const int* pred = (m + 1 < M) ? prog + (int64_t)c * M + m + 1 : nullptr;
-    int* mine = prog + (int64_t)c * M + m;
-    int known = pred ? 0 : INT32_MAX;  // rows known final w.r.t. earlier blocks
-    for (int64_t j = 0; j < J0; ++j) {
-      const int64_t row0 = s0 + 1 + j * NB;
-      // rows [row0, row0 + W) must be final w.r.t. block m+1
-      int64_t need = row0 + W;
-      if (need > n) need = n;
-      if (known < need) {
-        int p = load_progress(pred);
-        while (p < need) {
-          __builtin_amdgcn_s_sleep(1);
-          p = load_progress(pred);
-        }
-        known = p;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      }
-      E* __restrict__ rp = bp + row0 * 64;  // uniform
-      if (j == 0) {
-#pragma unroll
-        for (int i = 0; i < W; ++i) x[i] = rp[i * 64 + lane];
-      } else {
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i) x[i] = x[i + NB];
-#pragma unroll
-        for (int i = K - 1; i < W; ++i) x[i] = rp[i * 64 + lane];
-      }
-      // slot of reflector (s0+o, j), or slot 0 with tau = 0 if it does not exist
-      auto slot_of = [&](int o) -> int64_t {
-        const int64_t s = s0 + o;
-        const bool ok = (s <= s1) && (s + 1 + j * NB < n);
-        return ok ? ctot - csum(n - 1 - s, NB) + j : -1;
-      };
-      int64_t sl = slot_of(K - 1);
-      Chunk<E, ChunkSize<E>::value> cur =
-          load_chunk<E, ChunkSize<E>::value>(hh + (sl < 0 ? 0 : sl) * NB);
-      RevFor<K>::run([&](auto oc) {
-        constexpr int o = decltype(oc)::value;
-        const int64_t sn = (o > 0) ? slot_of(o - 1) : -1;
-        const int64_t su = sl < 0 ? 0 : sl;
-        const E t = sl < 0 ? O::zero() : tau[su];
-        apply_reflector<E, NB, W>(x, o, hh + su * NB, hh2 + su * NB,
-                                  hh + (sn < 0 ? 0 : sn) * NB, t, cur);
-        sl = sn;
-      });
-#pragma unroll
-      for (int i = 0; i < NB; ++i) rp[i * 64 + lane] = x[i];
-      if (j + 1 < J0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0)
-          __hip_atomic_store(mine, (int)(row0 + NB), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    const int64_t rowl = s0 + 1 + (J0 - 1) * NB;
-    E* __restrict__ rl = bp + rowl * 64;
-#pragma unroll
-    for (int i = NB; i < W; ++i) rl[i * 64 + lane] = x[i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(mine, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-}
-
 // Compile-time loop i = 0, 1, ..., N-1.
 template <int N, int I = 0>
 struct FwdFor {
@@ -338,131 +318,194 @@ struct FwdFor {
 };
 
 // ---------------------------------------------------------------------------
-// fp64 wavefront stripe kernel with DPP-broadcast reflector operands.
-// Same tasks, order, window and progress protocol as k_wave; the reflector
-// v (NB values) lives in NG = NB/16 VGPR pairs, lane l holding v[16g + l%16]
-// in pair g, and tau in a VGPR; both are loaded with vector loads one
-// reflector ahead.  The dot product uses NG independent accumulators (one per
-// 16-value segment).
+// One chase step of one block: apply the K reflectors (s0+o, j), o = K-1..0,
+// to the window x (rows row0 .. row0+W-1 of the lane's column).  A reflector
+// that does not exist is applied as slot 0 with tau = 0 (exact no-op on finite
+// data), which keeps the unrolled step free of branches.
 // ---------------------------------------------------------------------------
-template <int NB, int K, int OCC>
-__global__ __launch_bounds__(64, OCC) void k_wave_dpp(const double* __restrict__ hh,
-                                                      const double* __restrict__ tau,
-                                                      double* __restrict__ Qs, int64_t rows_pad,
-                                                      int64_t n, int G, int M,
-                                                      int* __restrict__ prog, int* ticket) {
-  static_assert(NB == 32 || NB == 64, "DPP kernel supports NB = 32, 64");
-  constexpr int NG = NB / 16;
-  constexpr int W = NB + K - 1;
-  const int lane = threadIdx.x;
-  const int l16 = lane & 15;
-  const int64_t ctot = csum(n - 1, NB);
-  const int ntask = G * M;
-  double x[W];
-  for (;;) {
-    const int tk = wave_ticket(ticket);
-    if (tk >= ntask) break;
-    const int m = M - 1 - tk / G;
-    const int c = tk - (tk / G) * G;
-    double* __restrict__ bp = Qs + (int64_t)c * rows_pad * 64;
-    const int64_t s0 = (int64_t)m * K;
-    const int64_t s1 = (s0 + K - 1 < n - 2) ? s0 + K - 1 : n - 2;
-    const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
-    const int* pred = (m + 1 < M) ? prog + (int64_t)c * M + m + 1 : nullptr;
-    int* mine = prog + (int64_t)c * M + m;
-    int known = pred ? 0 : INT32_MAX;
-    for (int64_t j = 0; j < J0; ++j) {
-      const int64_t row0 = s0 + 1 + j * NB;
-      int64_t need = row0 + W;
-      if (need > n) need = n;
-      if (known < need) {
-        int p = load_progress(pred);
-        while (p < need) {
-          __builtin_amdgcn_s_sleep(1);
-          p = load_progress(pred);
+template <typename E, int NB, int K>
+struct StepSmem {
+  static constexpr int W = NB + K - 1;
+  static __device__ __forceinline__ void run(E (&x)[W], const E* __restrict__ hh,
+                                             const E* __restrict__ hh2,
+                                             const E* __restrict__ tau, int64_t s0, int64_t s1,
+                                             int64_t j, int64_t n, int64_t ctot) {
+    using O = Ops<E>;
+    auto slot_of = [&](int o) -> int64_t {
+      const int64_t s = s0 + o;
+      const bool ok = (s <= s1) && (s + 1 + j * NB < n);
+      return ok ? ctot - csum(n - 1 - s, NB) + j : -1;
+    };
+    int64_t sl = slot_of(K - 1);
+    Chunk<E, ChunkSize<E>::value> cur =
+        load_chunk<E, ChunkSize<E>::value>(hh + (sl < 0 ? 0 : sl) * NB);
+    RevFor<K>::run([&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const int64_t sn = (o > 0) ? slot_of(o - 1) : -1;
+      const int64_t su = sl < 0 ? 0 : sl;
+      const E t = sl < 0 ? O::zero() : tau[su];
+      apply_reflector<E, NB, W>(x, o, hh + su * NB, hh2 + su * NB, hh + (sn < 0 ? 0 : sn) * NB,
+                                t, cur);
+      sl = sn;
+    });
+  }
+};
+
+// fp64: the reflector v (NB values) lives in NG = NB/16 VGPR pairs, lane l
+// holding v[16g + l%16] in pair g, and is fed to the FMAs by DPP
+// row_newbcast; v and tau are vector-loaded one reflector ahead.  NG
+// independent accumulators, one per 16-value segment.
+template <int NB, int K>
+struct StepDpp {
+  static constexpr int W = NB + K - 1;
+  static constexpr int NG = NB / 16;
+  static_assert(NB == 32 || NB == 64, "DPP step supports NB = 32, 64");
+  static __device__ __forceinline__ void run(double (&x)[W], const double* __restrict__ hh,
+                                             const double* __restrict__,
+                                             const double* __restrict__ tau, int64_t s0,
+                                             int64_t s1, int64_t j, int64_t n, int64_t ctot) {
+    const int l16 = threadIdx.x & 15;
+    auto slot_of = [&](int o) -> int64_t {
+      const int64_t s = s0 + o;
+      const bool ok = (s <= s1) && (s + 1 + j * NB < n);
+      return ok ? ctot - csum(n - 1 - s, NB) + j : -1;
+    };
+    double V[NG], T;
+    {
+      const int64_t sl = slot_of(K - 1);
+      const int64_t su = sl < 0 ? 0 : sl;
+      const double* __restrict__ p = hh + su * NB + l16;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) V[g] = p[16 * g];
+      const double tl = tau[su];
+      T = sl < 0 ? 0.0 : tl;
+    }
+    RevFor<K>::run([&](auto oc) {
+      constexpr int o = decltype(oc)::value;
+      const int64_t sn = (o > 0) ? slot_of(o - 1) : -1;
+      const int64_t snu = sn < 0 ? 0 : sn;
+      double Vn[NG], Tn = 0.0;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      FwdFor<16>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (NG == 4) {
+          dpp_dot4<i>(a0, a1, a2, a3, V[0], V[1], V[2], V[3], &x[o + i], &x[o + 16 + i],
+                      &x[o + 32 + i], &x[o + 48 + i]);
+        } else {
+          dpp_dot2<i>(a0, a1, V[0], V[1], &x[o + i], &x[o + 16 + i]);
         }
-        known = p;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-      }
-      double* __restrict__ rp = bp + row0 * 64;
-      if (j == 0) {
+        if constexpr (i == 0) {
+          // prefetch the next reflector; its address depends on a0 so the
+          // loads are issued here and not hoisted
+          const int z = zero_after(a0);
+          const double* __restrict__ p = hh + snu * NB + z + l16;
 #pragma unroll
-        for (int i = 0; i < W; ++i) x[i] = rp[i * 64 + lane];
-      } else {
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i) x[i] = x[i + NB];
-#pragma unroll
-        for (int i = K - 1; i < W; ++i) x[i] = rp[i * 64 + lane];
-      }
-      auto slot_of = [&](int o) -> int64_t {
-        const int64_t s = s0 + o;
-        const bool ok = (s <= s1) && (s + 1 + j * NB < n);
-        return ok ? ctot - csum(n - 1 - s, NB) + j : -1;
-      };
-      double V[NG], T;
-      {
-        const int64_t sl = slot_of(K - 1);
-        const int64_t su = sl < 0 ? 0 : sl;
-        const double* __restrict__ p = hh + su * NB + l16;
-#pragma unroll
-        for (int g = 0; g < NG; ++g) V[g] = p[16 * g];
-        const double tl = tau[su];
-        T = sl < 0 ? 0.0 : tl;
-      }
-      RevFor<K>::run([&](auto oc) {
-        constexpr int o = decltype(oc)::value;
-        const int64_t sn = (o > 0) ? slot_of(o - 1) : -1;
-        const int64_t snu = sn < 0 ? 0 : sn;
-        double Vn[NG], Tn = 0.0;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        FwdFor<16>::run([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          if constexpr (NG == 4) {
-            dpp_dot4<i>(a0, a1, a2, a3, V[0], V[1], V[2], V[3], &x[o + i], &x[o + 16 + i],
-                        &x[o + 32 + i], &x[o + 48 + i]);
-          } else {
-            dpp_dot2<i>(a0, a1, V[0], V[1], &x[o + i], &x[o + 16 + i]);
-          }
-          if constexpr (i == 0) {
-            // prefetch the next reflector; its address depends on a0 so the
-            // loads are issued here and not hoisted
-            const int z = zero_after(a0);
-            const double* __restrict__ p = hh + snu * NB + z + l16;
-#pragma unroll
-            for (int g = 0; g < NG; ++g) Vn[g] = p[16 * g];
-            const double tl = tau[snu + z];
-            Tn = sn < 0 ? 0.0 : tl;
-          }
-        });
-        const double nw = -(T * ((a0 + a1) + (a2 + a3)));
-        FwdFor<16>::run([&](auto ic) {
-          constexpr int i = decltype(ic)::value;
-          if constexpr (NG == 4) {
-            dpp_upd4<i>(x[o + i], x[o + 16 + i], x[o + 32 + i], x[o + 48 + i], V[0], V[1], V[2],
-                        V[3], nw);
-          } else {
-            dpp_upd2<i>(x[o + i], x[o + 16 + i], V[0], V[1], nw);
-          }
-        });
-#pragma unroll
-        for (int g = 0; g < NG; ++g) V[g] = Vn[g];
-        T = Tn;
+          for (int g = 0; g < NG; ++g) Vn[g] = p[16 * g];
+          const double tl = tau[snu + z];
+          Tn = sn < 0 ? 0.0 : tl;
+        }
+      });
+      const double nw = -(T * ((a0 + a1) + (a2 + a3)));
+      FwdFor<16>::run([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (NG == 4) {
+          dpp_upd4<i>(x[o + i], x[o + 16 + i], x[o + 32 + i], x[o + 48 + i], V[0], V[1], V[2],
+                      V[3], nw);
+        } else {
+          dpp_upd2<i>(x[o + i], x[o + 16 + i], V[0], V[1], nw);
+        }
       });
 #pragma unroll
-      for (int i = 0; i < NB; ++i) rp[i * 64 + lane] = x[i];
-      if (j + 1 < J0) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        if (lane == 0)
-          __hip_atomic_store(mine, (int)(row0 + NB), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-    }
-    const int64_t rowl = s0 + 1 + (J0 - 1) * NB;
-    double* __restrict__ rl = bp + rowl * 64;
-#pragma unroll
-    for (int i = NB; i < W; ++i) rl[i * 64 + lane] = x[i];
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-    if (lane == 0) __hip_atomic_store(mine, INT32_MAX, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int g = 0; g < NG; ++g) V[g] = Vn[g];
+      T = Tn;
+    });
   }
+};
+
+template <typename E, int NB, int K>
+struct StepFor {
+  using type = StepSmem<E, NB, K>;
+};
+template <int NB, int K>
+struct StepFor<double, NB, K> {
+  using type = StepDpp<NB, K>;
+};
+
+// ---------------------------------------------------------------------------
+// One tile: group q (chase steps [qS, min(qS+S, J0))) of block m on stripe c.
+//   Qs   stripe-major workspace, row r of stripe c at Qs + (c*rows_pad + r)*64
+// ---------------------------------------------------------------------------
+template <typename E, int NB, int K>
+__device__ __forceinline__ void run_tile(const E* __restrict__ hh, const E* __restrict__ hh2,
+                                         const E* __restrict__ tau, E* __restrict__ Qs,
+                                         int64_t rows_pad, int64_t n, int64_t c, int64_t m,
+                                         int64_t q, int64_t S) {
+  constexpr int W = NB + K - 1;
+  const int lane = threadIdx.x;
+  const int64_t ctot = csum(n - 1, NB);
+  E x[W];
+  // uniform base of the stripe; row r of the lane's column is bp[r*64 + lane]
+  E* __restrict__ bp = Qs + c * rows_pad * 64;
+  const int64_t s0 = m * K;
+  const int64_t s1 = (s0 + K - 1 < n - 2) ? s0 + K - 1 : n - 2;
+  const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
+  const int64_t j0 = q * S;
+  const int64_t j1 = (j0 + S < J0) ? j0 + S : J0;
+  for (int64_t j = j0; j < j1; ++j) {
+    const int64_t row0 = s0 + 1 + j * NB;
+    E* __restrict__ rp = bp + row0 * 64;  // uniform
+    if (j == j0) {
+#pragma unroll
+      for (int i = 0; i < W; ++i) x[i] = rp[i * 64 + lane];
+    } else {
+#pragma unroll
+      for (int i = 0; i < K - 1; ++i) x[i] = x[i + NB];
+#pragma unroll
+      for (int i = K - 1; i < W; ++i) x[i] = rp[i * 64 + lane];
+    }
+    StepFor<E, NB, K>::type::run(x, hh, hh2, tau, s0, s1, j, n, ctot);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) rp[i * 64 + lane] = x[i];
+  }
+  // rows carried to the next group (or final after the block's last step)
+  E* __restrict__ rl = bp + (s0 + 1 + (j1 - 1) * NB) * 64;
+#pragma unroll
+  for (int i = NB; i < W; ++i) rl[i * 64 + lane] = x[i];
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal-schedule kernels.  One problem: blockIdx.x = (block m0+i, stripe
+// c) over the launch's blocks; group q = t - (M-1-m).  Batched: the launch's
+// entries map blockIdx.x to (problem, block, stripe).  hh2 == hh (see
+// apply_reflector).
+// ---------------------------------------------------------------------------
+template <typename E, int NB, int K, int OCC>
+__global__ __launch_bounds__(64, OCC) void k_diag(const E* __restrict__ hh,
+                                                  const E* __restrict__ hh2,
+                                                  const E* __restrict__ tau, E* __restrict__ Qs,
+                                                  int64_t rows_pad, int64_t n, int G, int M,
+                                                  int t, int m0, int S) {
+  const int b = (int)blockIdx.x;
+  const int c = b % G;
+  const int m = m0 + b / G;
+  const int q = t - (M - 1 - m);
+  run_tile<E, NB, K>(hh, hh2, tau, Qs, rows_pad, n, c, m, q, S);
+}
+
+template <typename E, int NB, int K, int OCC>
+__global__ __launch_bounds__(64, OCC) void k_diag_b(const ProblemDesc* __restrict__ d,
+                                                    const DiagEntry* __restrict__ e, int ecount,
+                                                    int t) {
+  const int b = (int)blockIdx.x;
+  const int ei = find_by<DiagEntry, &DiagEntry::tile0>(e, ecount, b);
+  const DiagEntry& E0 = e[ei];
+  const ProblemDesc& P = d[E0.p];
+  const int local = b - E0.tile0;
+  const int c = local % P.G;
+  const int m = E0.m0 + local / P.G;
+  const int q = t - (P.M - 1 - m);
+  run_tile<E, NB, K>((const E*)P.hh, (const E*)P.hh, (const E*)P.tau, (E*)P.Qs, P.rows_pad, P.n,
+                     c, m, q, P.S);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,78 +520,194 @@ hipError_t launch_ref(const void* hh, const void* tau, void* Q, int64_t ldq, int
   return hipGetLastError();
 }
 
-// Workspace geometry of the stripe path.
-template <typename E, int NB, int K>
-void wave_geom(int64_t n, int64_t nev, int64_t* rows_pad, int64_t* G, int64_t* M,
-               size_t* qbytes, size_t* bytes) {
-  *G = (nev + 63) / 64;
-  *M = (n - 1 + K - 1) / K;
-  // deepest row touched: s0 + 1 + (J0-1)*NB + W - 1 < n + NB + K
-  *rows_pad = ((n + NB + K + 63) / 64) * 64;
-  *qbytes = (((size_t)(*rows_pad) * (size_t)(*G) * 64 * sizeof(E) + 255) / 256) * 256;
-  *bytes = *qbytes + ((size_t)(*G) * (size_t)(*M) + 64) * sizeof(int);
+inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+// Host-side geometry and diagonal schedule of one problem.
+struct DiagPlan {
+  int64_t n = 0, nev = 0, NB = 0, K = 0, S = 1;
+  int64_t G = 0, M = 0, rows_pad = 0, T = 0;
+  std::vector<int> Qm;  // groups of block m
+
+  DiagPlan(int64_t n_, int64_t nev_, int64_t NB_, int64_t K_, int64_t S_)
+      : n(n_), nev(nev_), NB(NB_), K(K_), S(S_) {
+    G = (nev + 63) / 64;
+    M = (n - 1 + K - 1) / K;
+    // deepest row touched: s0 + 1 + (J0-1)*NB + W - 1 < n + NB + K
+    rows_pad = ((n + NB + K + 63) / 64) * 64;
+    Qm.resize((size_t)M);
+    T = 0;
+    for (int64_t m = 0; m < M; ++m) {
+      const int64_t J0 = (n - 1 - m * K + NB - 1) / NB;
+      Qm[(size_t)m] = (int)((J0 + S - 1) / S);
+      T = std::max(T, (M - 1 - m) + Qm[(size_t)m]);
+    }
+  }
+  // blocks active at launch t: [m0, m0 + cnt)
+  void active(int64_t t, int64_t* m0, int64_t* cnt) const {
+    int64_t a = M - 1 - t;
+    if (a < 0) a = 0;
+    int64_t b = a;
+    while (b < M && t - (M - 1 - b) < Qm[(size_t)b]) ++b;
+    *m0 = a;
+    *cnt = b - a;
+  }
+  template <typename E>
+  size_t qbytes() const {
+    return align256((size_t)rows_pad * (size_t)G * 64 * sizeof(E));
+  }
+};
+
+// Chase steps per tile: the largest S (fewest launches and window reloads)
+// that still gives the middle launches several waves per SIMD slot.
+inline int64_t choose_steps(int64_t n, int64_t nev, int64_t NB, int64_t K, int num_cu, int occ) {
+  const int64_t G = (nev + 63) / 64;
+  const int64_t M = (n - 1 + K - 1) / K;
+  const int64_t J = (n - 1 + NB - 1) / NB;
+  const int64_t slots = (int64_t)num_cu * 4 * occ;
+  int64_t S = 16;
+  while (S > 1 && G * std::min(M, (J + S - 1) / S) < 4 * slots) S /= 2;
+  return S;
 }
 
-// Which kernel runs a (type, NB, K, OCC) variant: fp64 uses the DPP kernel.
 template <typename E, int NB, int K, int OCC>
-struct WaveKernel {
-  static void launch(dim3 g, hipStream_t st, const E* hh, const E* tau, E* Qs, int64_t rows_pad,
-                     int64_t n, int G, int M, int* prog, int* ticket) {
-    hipLaunchKernelGGL((k_wave<E, NB, K, OCC>), g, dim3(64), 0, st, hh, hh, tau, Qs, rows_pad, n,
-                       G, M, prog, ticket);
-  }
-};
-template <int NB, int K, int OCC>
-struct WaveKernel<double, NB, K, OCC> {
-  static void launch(dim3 g, hipStream_t st, const double* hh, const double* tau, double* Qs,
-                     int64_t rows_pad, int64_t n, int G, int M, int* prog, int* ticket) {
-    hipLaunchKernelGGL((k_wave_dpp<NB, K, OCC>), g, dim3(64), 0, st, hh, tau, Qs, rows_pad, n, G,
-                       M, prog, ticket);
-  }
-};
-
-template <typename E, int NB, int K, int OCC>
-hipError_t launch_wave(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
-                       int64_t nev, hipStream_t st, int num_cu) {
-  int64_t rows_pad, G, M;
-  size_t qbytes, bytes;
-  wave_geom<E, NB, K>(n, nev, &rows_pad, &G, &M, &qbytes, &bytes);
-  if (G * M + 64 >= INT32_MAX || n + NB + K >= INT32_MAX) return hipErrorInvalidValue;
-  void* ws = nullptr;
-  hipError_t err = hipMallocAsync(&ws, bytes, st);
+hipError_t launch_diag(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
+                       int64_t nev, int64_t S, hipStream_t st, int num_cu) {
+  if (S <= 0) S = choose_steps(n, nev, NB, K, num_cu, OCC);
+  const DiagPlan pl(n, nev, NB, K, S);
+  if (pl.G * pl.M >= INT32_MAX || n + NB + K >= INT32_MAX) return hipErrorInvalidValue;
+  E* Qs = nullptr;
+  hipError_t err = hipMallocAsync((void**)&Qs, pl.template qbytes<E>(), st);
   if (err != hipSuccess) return err;
-  E* Qs = (E*)ws;
-  int* prog = (int*)((char*)ws + qbytes);
-  int* ticket = prog + G * M;
-  const int64_t nint = G * M + 64;
-  hipLaunchKernelGGL(k_zero_i32, dim3((unsigned)((nint + 255) / 256)), dim3(256), 0, st, prog,
-                     nint);
-  hipLaunchKernelGGL(k_to_rows<E>, dim3((unsigned)(rows_pad / 64), (unsigned)G), dim3(256), 0, st,
-                     (const E*)Q, ldq, n, nev, Qs, rows_pad);
-  const int64_t want = (int64_t)num_cu * 4 * OCC;
-  const int64_t grid = (G * M < want) ? G * M : want;
-  WaveKernel<E, NB, K, OCC>::launch(dim3((unsigned)grid), st, (const E*)hh, (const E*)tau, Qs,
-                                    rows_pad, n, (int)G, (int)M, prog, ticket);
-  hipLaunchKernelGGL(k_from_rows<E>, dim3((unsigned)((n + 63) / 64), (unsigned)G), dim3(256), 0,
-                     st, (const E*)Qs, rows_pad, (E*)Q, ldq, n, nev);
+  hipLaunchKernelGGL(k_to_rows<E>, dim3((unsigned)(pl.rows_pad / 64), (unsigned)pl.G), dim3(256),
+                     0, st, (const E*)Q, ldq, n, nev, Qs, pl.rows_pad);
+  for (int64_t t = 0; t < pl.T; ++t) {
+    int64_t m0, cnt;
+    pl.active(t, &m0, &cnt);
+    if (cnt == 0) continue;
+    hipLaunchKernelGGL((k_diag<E, NB, K, OCC>), dim3((unsigned)(cnt * pl.G)), dim3(64), 0, st,
+                       (const E*)hh, (const E*)hh, (const E*)tau, Qs, pl.rows_pad, n, (int)pl.G,
+                       (int)pl.M, (int)t, (int)m0, (int)S);
+  }
+  hipLaunchKernelGGL(k_from_rows<E>, dim3((unsigned)((n + 63) / 64), (unsigned)pl.G), dim3(256),
+                     0, st, (const E*)Qs, pl.rows_pad, (E*)Q, ldq, n, nev);
+  err = hipGetLastError();
+  const hipError_t e2 = hipFreeAsync(Qs, st);
+  return err != hipSuccess ? err : e2;
+}
+
+// Batched launch: problems idx[0..cnt) of probs (all of element type E and
+// semi-bandwidth NB, validated by the caller): the diagonal schedules of all
+// problems run side by side, launch t holding launch t of every problem.
+template <typename E, int NB, int K, int OCC>
+hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
+                               int64_t S, hipStream_t st, int num_cu) {
+  std::vector<ProblemDesc> d;
+  std::vector<DiagPlan> plans;
+  d.reserve((size_t)cnt);
+  plans.reserve((size_t)cnt);
+  int64_t total_cols = 0;
+  for (int64_t i = 0; i < cnt; ++i) {
+    const elpa_hh_problem& p = probs[idx[i]];
+    if (p.n <= 1 || p.nev == 0) continue;
+    total_cols += p.nev;
+  }
+  for (int64_t i = 0; i < cnt; ++i) {
+    const elpa_hh_problem& p = probs[idx[i]];
+    if (p.n <= 1 || p.nev == 0) continue;
+    // all problems share the launch slots: size S from the batch's columns
+    const int64_t s = S > 0 ? S : choose_steps(p.n, total_cols, NB, K, num_cu, OCC);
+    plans.emplace_back(p.n, p.nev, NB, K, s);
+    ProblemDesc x{};
+    x.hh = p.hh;
+    x.tau = p.tau;
+    x.Q = p.Q;
+    x.n = p.n;
+    x.nev = p.nev;
+    x.ldq = p.ldq;
+    d.push_back(x);
+  }
+  if (d.empty()) return hipSuccess;
+  size_t qoff = 0, tiles = 0, otiles = 0;
+  int64_t T = 0;
+  std::vector<size_t> qat(d.size());
+  for (size_t i = 0; i < d.size(); ++i) {
+    const DiagPlan& pl = plans[i];
+    d[i].G = (int)pl.G;
+    d[i].M = (int)pl.M;
+    d[i].S = (int)pl.S;
+    d[i].rows_pad = pl.rows_pad;
+    d[i].tile0 = (int)tiles;
+    d[i].otile0 = (int)otiles;
+    tiles += (size_t)(pl.rows_pad / 64 * pl.G);
+    otiles += (size_t)((pl.n + 63) / 64 * pl.G);
+    qat[i] = qoff;
+    qoff += pl.template qbytes<E>();
+    T = std::max(T, pl.T);
+  }
+  // schedule entries of every launch, concatenated
+  std::vector<DiagEntry> ent;
+  std::vector<int64_t> eoff((size_t)T + 1, 0), etiles((size_t)T, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    eoff[(size_t)t] = (int64_t)ent.size();
+    int64_t tl = 0;
+    for (size_t i = 0; i < d.size(); ++i) {
+      int64_t m0, c;
+      plans[i].active(t, &m0, &c);
+      if (c == 0) continue;
+      ent.push_back(DiagEntry{(int)i, (int)m0, (int)c, (int)tl});
+      tl += c * plans[i].G;
+    }
+    etiles[(size_t)t] = tl;
+  }
+  eoff[(size_t)T] = (int64_t)ent.size();
+  if (tiles >= (size_t)INT32_MAX || otiles >= (size_t)INT32_MAX) return hipErrorInvalidValue;
+  for (int64_t x : etiles)
+    if (x >= INT32_MAX) return hipErrorInvalidValue;
+  const size_t dbytes = align256(d.size() * sizeof(ProblemDesc));
+  const size_t ebytes = align256(std::max<size_t>(1, ent.size()) * sizeof(DiagEntry));
+  char* ws = nullptr;
+  hipError_t err = hipMallocAsync((void**)&ws, dbytes + ebytes + qoff, st);
+  if (err != hipSuccess) return err;
+  for (size_t i = 0; i < d.size(); ++i) d[i].Qs = ws + dbytes + ebytes + qat[i];
+  // pageable sources: each copy is staged before hipMemcpyAsync returns
+  err = hipMemcpyAsync(ws, d.data(), d.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice, st);
+  if (err == hipSuccess && !ent.empty())
+    err = hipMemcpyAsync(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry),
+                         hipMemcpyHostToDevice, st);
+  if (err != hipSuccess) {
+    (void)hipFreeAsync(ws, st);
+    return err;
+  }
+  const ProblemDesc* dd = (const ProblemDesc*)ws;
+  const DiagEntry* de = (const DiagEntry*)(ws + dbytes);
+  const int count = (int)d.size();
+  hipLaunchKernelGGL(k_to_rows_b<E>, dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
+  for (int64_t t = 0; t < T; ++t) {
+    const int64_t ne = eoff[(size_t)t + 1] - eoff[(size_t)t];
+    if (ne == 0) continue;
+    hipLaunchKernelGGL((k_diag_b<E, NB, K, OCC>), dim3((unsigned)etiles[(size_t)t]), dim3(64), 0,
+                       st, dd, de + eoff[(size_t)t], (int)ne, (int)t);
+  }
+  hipLaunchKernelGGL(k_from_rows_b<E>, dim3((unsigned)otiles), dim3(256), 0, st, dd, count);
   err = hipGetLastError();
   const hipError_t e2 = hipFreeAsync(ws, st);
   return err != hipSuccess ? err : e2;
 }
 
-#define EHH_WAVE(E, DT, NB, K, OCC) {DT, NB, K, OCC, &launch_wave<E, NB, K, OCC>}
+#define EHH_DIAG(E, DT, NB, K, OCC) \
+  {DT, NB, K, OCC, &launch_diag<E, NB, K, OCC>, &launch_diag_batched<E, NB, K, OCC>}
 
 const StripeEntry* stripe_table(int* size) {
   static const StripeEntry table[] = {
-      EHH_WAVE(double, 0, 32, 8, 2),  EHH_WAVE(double, 0, 32, 16, 2),
-      EHH_WAVE(double, 0, 32, 32, 2), EHH_WAVE(double, 0, 32, 48, 1),
-      EHH_WAVE(double, 0, 64, 8, 2),  EHH_WAVE(double, 0, 64, 16, 2),
-      EHH_WAVE(double, 0, 64, 24, 2), EHH_WAVE(double, 0, 64, 32, 2),
-      EHH_WAVE(double, 0, 64, 40, 1), EHH_WAVE(double, 0, 64, 48, 1),
-      EHH_WAVE(float, 1, 32, 16, 2),  EHH_WAVE(float, 1, 32, 32, 2),
-      EHH_WAVE(float, 1, 64, 16, 2),  EHH_WAVE(float, 1, 64, 32, 1),
-      EHH_WAVE(z64, 2, 32, 4, 2),     EHH_WAVE(z64, 2, 32, 8, 1),
-      EHH_WAVE(z64, 2, 64, 2, 1),     EHH_WAVE(z64, 2, 64, 4, 1),
+      EHH_DIAG(double, 0, 32, 8, 2),  EHH_DIAG(double, 0, 32, 16, 2),
+      EHH_DIAG(double, 0, 32, 32, 2), EHH_DIAG(double, 0, 32, 48, 1),
+      EHH_DIAG(double, 0, 64, 8, 2),  EHH_DIAG(double, 0, 64, 16, 2),
+      EHH_DIAG(double, 0, 64, 24, 2), EHH_DIAG(double, 0, 64, 32, 2),
+      EHH_DIAG(double, 0, 64, 40, 1), EHH_DIAG(double, 0, 64, 48, 1),
+      EHH_DIAG(float, 1, 32, 16, 2),  EHH_DIAG(float, 1, 32, 32, 2),
+      EHH_DIAG(float, 1, 64, 16, 2),  EHH_DIAG(float, 1, 64, 32, 1),
+      EHH_DIAG(z64, 2, 32, 4, 2),     EHH_DIAG(z64, 2, 32, 8, 1),
+      EHH_DIAG(z64, 2, 64, 2, 1),     EHH_DIAG(z64, 2, 64, 4, 1),
   };
   *size = (int)(sizeof(table) / sizeof(table[0]));
   return table;

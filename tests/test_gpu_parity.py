@@ -24,10 +24,14 @@ KS = [1, 2, 4, 6, 8, 16, 24, 32, 48, 64]
 
 @pytest.fixture(scope="module")
 def torch_dev():
+    import time
+    t0 = time.time()
+    print("importing torch", flush=True)
     import torch
     assert torch.cuda.is_available(), "GPU tests need a GPU"
     import paper_1811_01277_amd as P
     P.library()
+    print(f"torch ready after {time.time() - t0:.1f} s", flush=True)
     return torch, torch.device("cuda:0")
 
 
