@@ -46,6 +46,8 @@
 #include "hh_dpp.h"
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -522,6 +524,64 @@ hipError_t launch_ref(const void* hh, const void* tau, void* Q, int64_t ldq, int
 
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Stream-ordered host->device upload of small host tables.  hipMemcpyAsync
+// from pageable memory copies at call time, but a destination obtained from
+// hipMallocAsync is only valid in stream order (earlier work on the stream may
+// still use the recycled memory), so tables are staged in pinned host buffers
+// and copied asynchronously; a buffer is reused only after the event recorded
+// behind its copy has completed.  One pool per device.
+class PinnedStaging {
+ public:
+  static PinnedStaging& for_device(int dev) {
+    static std::mutex mu;
+    static std::vector<PinnedStaging*> pools;
+    std::lock_guard<std::mutex> g(mu);
+    if (dev < 0) dev = 0;
+    if ((size_t)dev >= pools.size()) pools.resize((size_t)dev + 1, nullptr);
+    if (!pools[(size_t)dev]) pools[(size_t)dev] = new PinnedStaging();
+    return *pools[(size_t)dev];
+  }
+
+  // copy `bytes` from host `src` to device `dst` in stream order on `st`
+  hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
+    if (bytes == 0) return hipSuccess;
+    std::lock_guard<std::mutex> g(mu_);
+    Buf* b = nullptr;
+    for (Buf& x : bufs_) {
+      if (x.cap >= bytes && hipEventQuery(x.ev) == hipSuccess) {
+        b = &x;
+        break;
+      }
+    }
+    if (!b) {
+      Buf nb{};
+      nb.cap = std::max<size_t>(bytes, 1 << 16);
+      hipError_t e = hipHostMalloc(&nb.p, nb.cap, hipHostMallocDefault);
+      if (e != hipSuccess) return e;
+      e = hipEventCreateWithFlags(&nb.ev, hipEventDisableTiming);
+      if (e != hipSuccess) {
+        (void)hipHostFree(nb.p);
+        return e;
+      }
+      bufs_.push_back(nb);
+      b = &bufs_.back();
+    }
+    std::memcpy(b->p, src, bytes);
+    hipError_t e = hipMemcpyAsync(dst, b->p, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return hipEventRecord(b->ev, st);
+  }
+
+ private:
+  struct Buf {
+    void* p;
+    size_t cap;
+    hipEvent_t ev;
+  };
+  std::mutex mu_;
+  std::vector<Buf> bufs_;
+};
+
 // Host-side geometry and diagonal schedule of one problem.
 struct DiagPlan {
   int64_t n = 0, nev = 0, NB = 0, K = 0, S = 1;
@@ -669,11 +729,12 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
   hipError_t err = hipMallocAsync((void**)&ws, dbytes + ebytes + qoff, st);
   if (err != hipSuccess) return err;
   for (size_t i = 0; i < d.size(); ++i) d[i].Qs = ws + dbytes + ebytes + qat[i];
-  // pageable sources: each copy is staged before hipMemcpyAsync returns
-  err = hipMemcpyAsync(ws, d.data(), d.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice, st);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  PinnedStaging& stage = PinnedStaging::for_device(dev);
+  err = stage.upload(ws, d.data(), d.size() * sizeof(ProblemDesc), st);
   if (err == hipSuccess && !ent.empty())
-    err = hipMemcpyAsync(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry),
-                         hipMemcpyHostToDevice, st);
+    err = stage.upload(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry), st);
   if (err != hipSuccess) {
     (void)hipFreeAsync(ws, st);
     return err;
