@@ -60,7 +60,8 @@ def test_batch_matches_oracle_and_single_calls(torch_dev):
         host.append(h)
     singles = []
     for (q, h, t, nbw) in probs:
-        qq = q.t().contiguous().t()
+        qq = q.clone()  # new storage, same column-major strides
+        assert qq.data_ptr() != q.data_ptr() and qq.stride() == q.stride()
         P.hh_trafo(qq, h, t, nbw)
         singles.append(qq)
     print("batch of", len(probs), "problems", flush=True)
