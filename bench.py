@@ -36,13 +36,44 @@ def parse():
     ap.add_argument("--nbw", type=int, default=64)
     ap.add_argument("--nev", type=int, default=20000)
     ap.add_argument("--dtype", default="r64", choices=["r64", "r32", "c64"])
-    ap.add_argument("--path", type=int, default=0, help="0 auto, 1 ref, 2 stripe")
+    ap.add_argument("--path", type=int, default=0,
+                    help="0 auto, 1 reference, 2 one-lane stripe, 3 two-lane stripe")
     ap.add_argument("--k", type=int, default=0, help="sweeps fused per pass (0 = auto)")
+    ap.add_argument("--tile-steps", type=int, default=0,
+                    help="chase steps per tile of the launch schedule (0 = auto)")
+    ap.add_argument("--streams", type=int, default=0,
+                    help="stripe groups on concurrent streams (0 = auto)")
     ap.add_argument("--seed", type=int, default=301)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="instead of the benchmark: copy a MIB-MiB device buffer 3 times "
+                         "(reference kernel of known size for the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size (read mib MiB, write mib MiB).
+    Under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its counters give the factor
+    from counter units to bytes for this GPU."""
+    import torch
+    dev = torch.device("cuda:0")
+    n = mib * (1 << 20) // 8
+    a = torch.empty(n, dtype=torch.float64, device=dev).uniform_()
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    for i in range(3):
+        b.copy_(a)
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(3)]
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8,
+                      "ms": [round(x, 4) for x in ms],
+                      "GBps_read_plus_write": round(2 * n * 8 / (min(ms) * 1e-3) / 1e9, 1)}),
+          flush=True)
 
 
 def counted_flops(n, nev, dt):
@@ -85,6 +116,9 @@ def cpu_baseline(args, hh, tau, Z):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the path shards by columns across GPUs by design, "
@@ -107,9 +141,13 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
 
+    plan = dict(path=args.path, k=args.k, steps=args.tile_steps, streams=args.streams)
     for _ in range(args.warmup):
-        P.hh_trafo(q, h, t, nbw, stream=stream, path=args.path, k=args.k)
+        P.hh_trafo(q, h, t, nbw, stream=stream, **plan)
     torch.cuda.synchronize()
+    # library-side HIP events on the launch stream around the main kernel
+    # sequence of every call (the latest call's figures are read below)
+    P.profile_enable(True)
 
     starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
     ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
@@ -117,16 +155,24 @@ def main():
     w0 = time.perf_counter()
     for i in range(args.steps):
         starts[i].record(stream)
-        P.hh_trafo(q, h, t, nbw, stream=stream, path=args.path, k=args.k)
+        P.hh_trafo(q, h, t, nbw, stream=stream, **plan)
         ends[i].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
-    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]  # ms per launch
+    prof = P.profile_last()  # last timed step: main kernel sequence
+    P.profile_enable(False)
+    per = [s.elapsed_time(e) for s, e in zip(starts, ends)]  # ms per call
     ms = wall * 1e3 / args.steps
     flops = counted_flops(n, nev, dt)
-    avg_kernel_ms = float(np.mean(per))
-    achieved = flops / (avg_kernel_ms * 1e-3) / 1e12
+    # algorithmic flops per launch / average launch duration, times the
+    # launches in flight (stripe groups on concurrent streams overlap their
+    # launches): the dominant kernel's device-wide rate, flops / sequence time
+    launches = max(1, prof["launches"])
+    avg_launch_ms = prof["sum_launch_ms"] / launches
+    in_flight = prof["sum_launch_ms"] / prof["kernel_ms"]
+    achieved = (flops / launches) / (avg_launch_ms * 1e-3) * in_flight / 1e12
     peak = PEAK_TFLOPS[dt]
+    kname = {1: "k_ref", 2: "k_diag", 3: "k_split"}.get(prof["path"], "?")
     value = flops / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
@@ -135,11 +181,17 @@ def main():
         "dtype": {"r64": "f64", "r32": "f32", "c64": "c128"}[dt], "data": "synthetic",
         "config": {"workload": f"tridiag->band back-transform, n={n}, nbw={nbw}, nev={nev}, "
                                f"{dt}, synthetic reflectors", "n": n, "nbw": nbw, "nev": nev,
-                   "plan": {"path": args.path, "k": args.k}},
+                   "plan": {"path": prof["path"], "k": prof["k"], "tile_steps": prof["steps"],
+                            "streams": prof["streams"]}},
         "pct_fp64_peak": round(100.0 * achieved / PEAK_TFLOPS["r64"], 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "kernel_ms": [round(x, 3) for x in per]},
+                     "kernel": kname, "launches": prof["launches"],
+                     "avg_launch_us": round(avg_launch_ms * 1e3, 2),
+                     "launches_in_flight": round(in_flight, 3),
+                     "sequence_ms": round(prof["kernel_ms"], 3),
+                     "flops_per_launch": flops / launches,
+                     "call_ms": [round(x, 3) for x in per]},
     }
     if not args.no_cpu:
         del q, h, t

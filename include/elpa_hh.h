@@ -67,21 +67,42 @@ enum {
 enum {
     ELPA_PATH_AUTO = 0,   /* library choice */
     ELPA_PATH_REF = 1,    /* one reflector at a time, any nbw */
-    ELPA_PATH_STRIPE = 2  /* register-window stripe kernel, k sweeps fused */
+    ELPA_PATH_STRIPE = 2, /* register-window stripe kernel, k sweeps fused, one lane
+                             per column (all element types) */
+    ELPA_PATH_SPLIT = 3   /* register-window stripe kernel, k sweeps fused, two lanes
+                             per column and reflectors pre-packed in consumption order
+                             (real fp64, nbw 32 or 64; the fp64 default) */
+};
+
+/* order of the tiles of one launch over the workgroup ids (elpa_hh_plan.order) */
+enum {
+    ELPA_ORDER_AUTO = 0,   /* library choice */
+    ELPA_ORDER_LINEAR = 1, /* tile (block m, stripe c) at id (m - m0) * stripes + c */
+    ELPA_ORDER_XCD = 2     /* ids dealt to the 8 accelerator dies (XCDs) round robin
+                              each get a contiguous run of tiles, so the tiles that
+                              share a sweep block's reflectors share one die's L2 */
 };
 
 /*
  * Explicit execution plan (tests, autotuning).  Zero fields mean "library
- * default".  path: ELPA_PATH_*; k: sweeps fused per pass (the stripe kernel
- * keeps an (nbw + k - 1)-row window per column in registers); steps: chase
- * steps per tile of the stripe kernel's launch schedule (fewer steps: more
- * tiles per launch, more launches).
+ * default".  path: ELPA_PATH_*; k: sweeps fused per pass (the stripe kernels
+ * keep an (nbw + k - 1)-row window per column in registers; each row loaded
+ * from memory meets k reflectors); steps: chase steps per tile of the stripe
+ * kernels' launch schedule (fewer steps: more tiles per launch, more
+ * launches); order: ELPA_ORDER_* ; streams: the stripes (independent
+ * column groups) are split into this many groups whose launch sequences run
+ * on concurrent library-owned streams, forked from and joined back into the
+ * caller's stream (1 = everything on the caller's stream; at most 8;
+ * 0 = library choice, 2).
+ * Results do not depend on order or streams.
  */
 typedef struct {
     int32_t path;
     int32_t k;
     int32_t steps;
-    int32_t reserved;
+    int32_t order;
+    int32_t streams;
+    int32_t reserved;   /* must be 0 */
 } elpa_hh_plan;
 
 /*
@@ -146,6 +167,32 @@ int elpa_hh_trafo_batched(const elpa_hh_problem *probs, int64_t count, void *str
  * Whether an explicit plan can run (n, nbw, dtype): 1 yes, 0 no.
  */
 int elpa_hh_plan_supported(int64_t nbw, int32_t dtype, const elpa_hh_plan *plan);
+
+/*
+ * Kernel timing (benchmarks, tests).  While enabled on a host thread, every
+ * call made from that thread on the device that was current at enable time
+ * records HIP events around its main kernel sequence (the tile launches of
+ * the stripe paths, the launch of the reference path) on the caller's stream,
+ * and around each of those launches on the stream it runs on.
+ * elpa_hh_profile_last waits for the latest such call's events and reports;
+ * ELPA_ERR_ARG if no call was recorded since enabling.
+ * elpa_hh_profile_enable(0) disables and releases the events.
+ * With several stripe-group streams, launches overlap: sum_launch_ms /
+ * kernel_ms is the average number of launches in flight.
+ */
+typedef struct {
+    double kernel_ms;     /* event time of the whole main kernel sequence */
+    int64_t launches;     /* main-kernel launches in that time */
+    int32_t path;         /* ELPA_PATH_* that ran */
+    int32_t k;            /* sweeps fused per pass (0: reference path) */
+    int64_t steps;        /* chase steps per tile (0: reference path) */
+    double sum_launch_ms; /* sum over launches of each launch's event time */
+    int32_t streams;      /* stripe-group streams used */
+    int32_t reserved;
+} elpa_hh_profile;
+
+int elpa_hh_profile_enable(int on);
+int elpa_hh_profile_last(elpa_hh_profile *out);
 
 /* Static message for a return code (never NULL). */
 const char *elpa_strerror(int code);

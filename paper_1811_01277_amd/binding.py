@@ -6,7 +6,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libelpahip.so"
 
 R64, R32, C64 = 0, 1, 2
-PATH_AUTO, PATH_REF, PATH_STRIPE = 0, 1, 2
+PATH_AUTO, PATH_REF, PATH_STRIPE, PATH_SPLIT = 0, 1, 2, 3
+ORDER_AUTO, ORDER_LINEAR, ORDER_XCD = 0, 1, 2
 
 _lib = None
 
@@ -19,13 +20,19 @@ class ElpaError(RuntimeError):
 
 class _Plan(C.Structure):
     _fields_ = [("path", C.c_int32), ("k", C.c_int32), ("steps", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("order", C.c_int32), ("streams", C.c_int32), ("reserved", C.c_int32)]
 
 
 class _Problem(C.Structure):
     _fields_ = [("n", C.c_int64), ("nev", C.c_int64), ("nbw", C.c_int64), ("ldq", C.c_int64),
                 ("hh", C.c_void_p), ("tau", C.c_void_p), ("Q", C.c_void_p),
                 ("dtype", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Profile(C.Structure):
+    _fields_ = [("kernel_ms", C.c_double), ("launches", C.c_int64), ("path", C.c_int32),
+                ("k", C.c_int32), ("steps", C.c_int64), ("sum_launch_ms", C.c_double),
+                ("streams", C.c_int32), ("reserved", C.c_int32)]
 
 
 def library_path():
@@ -53,12 +60,35 @@ def library():
         L.elpa_hh_trafo_batched.restype = C.c_int
         L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
         L.elpa_hh_plan_supported.restype = C.c_int
+        L.elpa_hh_profile_enable.argtypes = [C.c_int]
+        L.elpa_hh_profile_enable.restype = C.c_int
+        L.elpa_hh_profile_last.argtypes = [C.POINTER(_Profile)]
+        L.elpa_hh_profile_last.restype = C.c_int
         L.elpa_strerror.argtypes = [C.c_int]
         L.elpa_strerror.restype = C.c_char_p
         L.elpa_hh_version.argtypes = []
         L.elpa_hh_version.restype = C.c_char_p
         _lib = L
     return _lib
+
+
+def profile_enable(on=True):
+    """Enable (or disable) kernel timing of the calls made from this thread."""
+    rc = library().elpa_hh_profile_enable(1 if on else 0)
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+
+
+def profile_last():
+    """Timing of the latest call's main kernel sequence (waits for it):
+    dict(kernel_ms, launches, path, k, steps, sum_launch_ms, streams)."""
+    out = _Profile()
+    rc = library().elpa_hh_profile_last(C.byref(out))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    return {"kernel_ms": out.kernel_ms, "launches": out.launches, "path": out.path,
+            "k": out.k, "steps": out.steps, "sum_launch_ms": out.sum_launch_ms,
+            "streams": out.streams}
 
 
 def strerror(code):
@@ -77,10 +107,11 @@ def slot_offset(n, nbw, s):
     return int(library().elpa_hh_slot_offset(n, nbw, s))
 
 
-def _plan(path, k, steps=0):
-    if path is None and not k and not steps:
+def _plan(path, k, steps=0, order=0, streams=0):
+    if path is None and not k and not steps and not order and not streams:
         return None
-    return _Plan(int(path or 0), int(k or 0), int(steps or 0), 0)
+    return _Plan(int(path or 0), int(k or 0), int(steps or 0), int(order or 0),
+                 int(streams or 0), 0)
 
 
 def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
@@ -88,9 +119,10 @@ def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
     return bool(library().elpa_hh_plan_supported(nbw, dtype, C.byref(pl) if pl else None))
 
 
-def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0, steps=0):
+def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0, steps=0,
+                 order=0, streams=0):
     """Raw-pointer entry: returns the library's status code (no raise)."""
-    pl = _plan(path, k, steps)
+    pl = _plan(path, k, steps, order, streams)
     return int(library().elpa_hh_trafo_plan(
         n, nev, nbw, C.c_void_p(hh), C.c_void_p(tau), C.c_void_p(q), ldq, dtype,
         C.c_void_p(stream), C.byref(pl) if pl is not None else None))
@@ -104,7 +136,7 @@ def _dtype_code(t):
     return m[t.dtype]
 
 
-def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0):
+def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0, order=0, streams=0):
     """Q <- H(0,0) ... H(n-2,J-1) Q in place on a column-major torch tensor.
 
     q:   (n, nev) device tensor with q.stride(0) == 1 (column major, ldq =
@@ -112,6 +144,8 @@ def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0):
     hh:  1-D contiguous tensor of N_refl*nbw reflector entries (same dtype).
     tau: 1-D contiguous tensor of N_refl scalars (same dtype).
     stream: torch.cuda.Stream or raw hipStream_t int; default: current stream.
+    path, k, steps, order, streams: explicit plan (elpa_hh_plan); 0 / None =
+    library choice.
     """
     import torch
     if q.dim() != 2:
@@ -138,13 +172,13 @@ def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0):
     else:
         st = stream.cuda_stream
     rc = hh_trafo_ptr(n, nev, nbw, hh.data_ptr(), tau.data_ptr(), q.data_ptr(), ldq, dt, st,
-                      path, k, steps)
+                      path, k, steps, order, streams)
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
     return q
 
 
-def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0):
+def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, streams=0):
     """Batched Q <- H ... H Q over a list of (q, hh, tau, nbw) tensor tuples.
 
     Each q is a column-major (n, nev) device tensor as in hh_trafo; problems
@@ -173,7 +207,7 @@ def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0):
         st = stream
     else:
         st = stream.cuda_stream
-    pl = _plan(path, k, steps)
+    pl = _plan(path, k, steps, order, streams)
     rc = int(library().elpa_hh_trafo_batched(arr, len(problems), C.c_void_p(st),
                                               C.byref(pl) if pl is not None else None))
     if rc != 0:

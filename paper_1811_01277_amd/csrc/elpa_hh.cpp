@@ -23,28 +23,78 @@ int64_t elem_size(int32_t dtype) {
   }
 }
 
-const ehh::StripeEntry* find_stripe(int32_t dtype, int64_t nb, int k) {
+const ehh::StripeEntry* find_entry(int path, int32_t dtype, int64_t nb, int k) {
   int cnt = 0;
-  const ehh::StripeEntry* tab = ehh::stripe_table(&cnt);
+  const ehh::StripeEntry* tab =
+      path == ELPA_PATH_SPLIT ? ehh::split_table(&cnt) : ehh::stripe_table(&cnt);
   for (int i = 0; i < cnt; ++i) {
     const ehh::StripeEntry& e = tab[i];
-    if (e.dtype == dtype && e.nb == nb && e.k == k) return &e;
+    if (e.path == path && e.dtype == dtype && e.nb == nb && e.k == k) return &e;
   }
   return nullptr;
 }
 
-// Default number of fused sweeps per pass for the stripe kernel.
-int default_k(int32_t dtype, int64_t nb) {
-  const int pref[] = {32, 16, 8, 4};
-  const int prefc[] = {4, 2};
-  if (dtype == ELPA_C64) {
-    for (int k : prefc)
-      if (find_stripe(dtype, nb, k)) return k;
+// Library default of the sweeps fused per pass, per kernel family: the first
+// compiled entry in order of preference (0 if none).
+int default_k(int path, int32_t dtype, int64_t nb) {
+  static const int split_pref[] = {64, 48, 80, 32, 96};
+  static const int stripe_pref[] = {32, 16, 8, 4};
+  static const int stripe_pref_c[] = {4, 2};
+  if (path == ELPA_PATH_SPLIT) {
+    for (int k : split_pref)
+      if (find_entry(path, dtype, nb, k)) return k;
     return 0;
   }
-  for (int k : pref)
-    if (find_stripe(dtype, nb, k)) return k;
+  if (dtype == ELPA_C64) {
+    for (int k : stripe_pref_c)
+      if (find_entry(path, dtype, nb, k)) return k;
+    return 0;
+  }
+  for (int k : stripe_pref)
+    if (find_entry(path, dtype, nb, k)) return k;
   return 0;
+}
+
+// Kernel that runs (dtype, nb) under `plan` (NULL = library choice).  Returns
+// the table entry, or nullptr with *path = ELPA_PATH_REF for the reference
+// kernel; *rc = ELPA_ERR_PLAN if an explicit plan cannot run.
+const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* plan, int* path,
+                                int* rc) {
+  *rc = ELPA_OK;
+  if (plan && (plan->order < ELPA_ORDER_AUTO || plan->order > ELPA_ORDER_XCD ||
+               plan->streams < 0 || plan->streams > 8 || plan->reserved != 0)) {
+    *rc = ELPA_ERR_PLAN;
+    return nullptr;
+  }
+  const int want = plan ? plan->path : ELPA_PATH_AUTO;
+  const int k = (plan && plan->k > 0) ? plan->k : 0;
+  *path = ELPA_PATH_REF;
+  switch (want) {
+    case ELPA_PATH_REF: return nullptr;
+    case ELPA_PATH_STRIPE:
+    case ELPA_PATH_SPLIT: {
+      const int kk = k ? k : default_k(want, dtype, nb);
+      const ehh::StripeEntry* e = kk ? find_entry(want, dtype, nb, kk) : nullptr;
+      if (!e) {
+        *rc = ELPA_ERR_PLAN;
+        return nullptr;
+      }
+      *path = want;
+      return e;
+    }
+    case ELPA_PATH_AUTO: {
+      for (int fam : {ELPA_PATH_SPLIT, ELPA_PATH_STRIPE}) {
+        const int kk = k ? k : default_k(fam, dtype, nb);
+        const ehh::StripeEntry* e = kk ? find_entry(fam, dtype, nb, kk) : nullptr;
+        if (e) {
+          *path = fam;
+          return e;
+        }
+      }
+      return nullptr;
+    }
+    default: *rc = ELPA_ERR_PLAN; return nullptr;
+  }
 }
 
 // Compute-unit count of the current device (cached per device id).
@@ -61,6 +111,16 @@ int device_cus() {
     cache[dev] = cu;
   }
   return cache[dev];
+}
+
+// Tile options of a plan (NULL = library choice).
+ehh::TileOpts tile_opts(const elpa_hh_plan* plan) {
+  ehh::TileOpts o{};
+  o.steps = plan ? plan->steps : 0;
+  o.xcd = (plan && plan->order == ELPA_ORDER_XCD) ? 8 : 1;
+  // two stripe groups by default: one group's launch tails overlap the other's
+  o.streams = (plan && plan->streams > 0) ? plan->streams : 2;
+  return o;
 }
 
 bool aligned(const void* p, int64_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -81,7 +141,26 @@ int validate(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* ta
   return ELPA_OK;
 }
 
+// A new call: forget the previous call's events.
+void prof_begin_call(int path) {
+  ehh::ProfState& p = ehh::prof_state();
+  if (!p.on) return;
+  p.started = p.recorded = false;
+  p.launches = 0;
+  p.path = path;
+  p.k = 0;
+  p.steps = 0;
+  p.streams = 1;
+}
+
 }  // namespace
+
+namespace ehh {
+ProfState& prof_state() {
+  static thread_local ProfState s;
+  return s;
+}
+}  // namespace ehh
 
 extern "C" {
 
@@ -98,16 +177,9 @@ int64_t elpa_hh_slot_offset(int64_t n, int64_t nbw, int64_t s) {
 
 int elpa_hh_plan_supported(int64_t nbw, int32_t dtype, const elpa_hh_plan* plan) {
   if (elem_size(dtype) == 0 || nbw < 1) return 0;
-  const int path = plan ? plan->path : ELPA_PATH_AUTO;
-  switch (path) {
-    case ELPA_PATH_AUTO:
-    case ELPA_PATH_REF: return 1;
-    case ELPA_PATH_STRIPE: {
-      const int k = (plan && plan->k > 0) ? plan->k : default_k(dtype, nbw);
-      return (k > 0 && find_stripe(dtype, nbw, k)) ? 1 : 0;
-    }
-    default: return 0;
-  }
+  int path = 0, rc = 0;
+  (void)resolve(dtype, nbw, plan, &path, &rc);
+  return rc == ELPA_OK ? 1 : 0;
 }
 
 int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau,
@@ -115,28 +187,20 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
                        const elpa_hh_plan* plan) {
   int rc = validate(n, nev, nbw, hh, tau, Q, ldq, dtype);
   if (rc != ELPA_OK) return rc;
+  int path = 0;
+  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc);
+  if (rc != ELPA_OK) return rc;
   if (n <= 1 || nev == 0) return ELPA_OK;
-  if (plan && plan->path != ELPA_PATH_AUTO && plan->path != ELPA_PATH_REF &&
-      plan->path != ELPA_PATH_STRIPE)
-    return ELPA_ERR_PLAN;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  int path = plan ? plan->path : ELPA_PATH_AUTO;
-  int k = (plan && plan->k > 0) ? plan->k : 0;
-  const ehh::StripeEntry* se = nullptr;
-  if (path == ELPA_PATH_AUTO) {
-    const int kd = k ? k : default_k(dtype, nbw);
-    se = kd ? find_stripe(dtype, nbw, kd) : nullptr;
-    path = se ? ELPA_PATH_STRIPE : ELPA_PATH_REF;
-  } else if (path == ELPA_PATH_STRIPE) {
-    const int kd = k ? k : default_k(dtype, nbw);
-    se = kd ? find_stripe(dtype, nbw, kd) : nullptr;
-    if (!se) return ELPA_ERR_PLAN;
-  }
+  prof_begin_call(path);
   hipError_t err;
-  if (path == ELPA_PATH_STRIPE) {
-    err = se->fn(hh, tau, Q, ldq, n, nev, plan ? plan->steps : 0, st, device_cus());
+  if (se) {
+    err = se->fn(hh, tau, Q, ldq, n, nev, tile_opts(plan), st, device_cus());
   } else {
+    ehh::ProfScope prof(st, 0, 0);
+    prof.before(st);
     err = ehh::ref_launcher(dtype)(hh, tau, Q, ldq, n, nev, nbw, st);
+    prof.after(st);
   }
   return err == hipSuccess ? ELPA_OK : ELPA_ERR_DEVICE;
 }
@@ -144,44 +208,49 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
 int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* stream,
                           const elpa_hh_plan* plan) {
   if (count < 0 || (count > 0 && !probs)) return ELPA_ERR_ARG;
-  if (plan && plan->path != ELPA_PATH_AUTO && plan->path != ELPA_PATH_REF &&
-      plan->path != ELPA_PATH_STRIPE)
-    return ELPA_ERR_PLAN;
+  if (plan && (plan->path < ELPA_PATH_AUTO || plan->path > ELPA_PATH_SPLIT)) return ELPA_ERR_PLAN;
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
     const int rc = validate(p.n, p.nev, p.nbw, p.hh, p.tau, p.Q, p.ldq, p.dtype);
     if (rc != ELPA_OK) return rc;
   }
-  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  const int path = plan ? plan->path : ELPA_PATH_AUTO;
-  const int kreq = (plan && plan->k > 0) ? plan->k : 0;
-  // group by (dtype, nbw); groups without a stripe kernel go one by one
+  // group by (dtype, nbw): one launch sequence per group with a stripe kernel,
+  // the reference kernel one problem at a time otherwise
   std::map<std::pair<int32_t, int64_t>, std::vector<int64_t>> groups;
+  std::map<std::pair<int32_t, int64_t>, const ehh::StripeEntry*> entry;
   std::vector<int64_t> singles;
+  int last_path = ELPA_PATH_REF;
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
+    int path = 0, rc = 0;
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, plan, &path, &rc);
+    if (rc != ELPA_OK) return rc;
     if (p.n <= 1 || p.nev == 0) continue;
-    const int k = kreq ? kreq : default_k(p.dtype, p.nbw);
-    const bool stripe = path != ELPA_PATH_REF && k > 0 && find_stripe(p.dtype, p.nbw, k);
-    if (path == ELPA_PATH_STRIPE && !stripe) return ELPA_ERR_PLAN;
-    if (stripe)
+    last_path = path;
+    if (se) {
       groups[{p.dtype, p.nbw}].push_back(i);
-    else
+      entry[{p.dtype, p.nbw}] = se;
+    } else {
       singles.push_back(i);
+    }
   }
-  const int cus = count > 0 ? device_cus() : 0;
+  if (groups.empty() && singles.empty()) return ELPA_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(groups.size() + singles.size() == 1 ? last_path : ELPA_PATH_AUTO);
+  const int cus = device_cus();
   for (auto& kv : groups) {
-    const int k = kreq ? kreq : default_k(kv.first.first, kv.first.second);
-    const ehh::StripeEntry* se = find_stripe(kv.first.first, kv.first.second, k);
-    const hipError_t err =
-        se->batched(probs, kv.second.data(), (int64_t)kv.second.size(),
-                    plan ? plan->steps : 0, st, cus);
+    const ehh::StripeEntry* se = entry[kv.first];
+    const hipError_t err = se->batched(probs, kv.second.data(), (int64_t)kv.second.size(),
+                                       tile_opts(plan), st, cus);
     if (err != hipSuccess) return ELPA_ERR_DEVICE;
   }
   for (int64_t i : singles) {
     const elpa_hh_problem& p = probs[i];
+    ehh::ProfScope prof(st, 0, 0);
+    prof.before(st);
     const hipError_t err =
         ehh::ref_launcher(p.dtype)(p.hh, p.tau, p.Q, p.ldq, p.n, p.nev, p.nbw, st);
+    prof.after(st);
     if (err != hipSuccess) return ELPA_ERR_DEVICE;
   }
   return ELPA_OK;
@@ -190,6 +259,49 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
 int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau, void* Q,
                   int64_t ldq, int32_t dtype, void* stream) {
   return elpa_hh_trafo_plan(n, nev, nbw, hh, tau, Q, ldq, dtype, stream, nullptr);
+}
+
+int elpa_hh_profile_enable(int on) {
+  ehh::ProfState& p = ehh::prof_state();
+  if (p.a) (void)hipEventDestroy(p.a);
+  if (p.b) (void)hipEventDestroy(p.b);
+  for (hipEvent_t e : p.ev) (void)hipEventDestroy(e);
+  p = ehh::ProfState{};
+  if (!on) return ELPA_OK;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return ELPA_ERR_DEVICE;
+  if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) {
+    if (p.a) (void)hipEventDestroy(p.a);
+    p = ehh::ProfState{};
+    return ELPA_ERR_DEVICE;
+  }
+  p.dev = dev;
+  p.on = true;
+  return ELPA_OK;
+}
+
+int elpa_hh_profile_last(elpa_hh_profile* out) {
+  ehh::ProfState& p = ehh::prof_state();
+  if (!out || !p.on || !p.recorded) return ELPA_ERR_ARG;
+  float ms = 0.f;
+  if (hipEventSynchronize(p.b) != hipSuccess || hipEventElapsedTime(&ms, p.a, p.b) != hipSuccess)
+    return ELPA_ERR_DEVICE;
+  double sum = 0.0;
+  for (int64_t i = 0; i < p.launches; ++i) {
+    float d = 0.f;
+    if (hipEventElapsedTime(&d, p.ev[2 * (size_t)i], p.ev[2 * (size_t)i + 1]) != hipSuccess)
+      return ELPA_ERR_DEVICE;
+    sum += d;
+  }
+  out->kernel_ms = ms;
+  out->launches = p.launches;
+  out->path = p.path;
+  out->k = p.k;
+  out->steps = p.steps;
+  out->sum_launch_ms = sum;
+  out->streams = p.streams;
+  out->reserved = 0;
+  return ELPA_OK;
 }
 
 const char* elpa_strerror(int code) {
@@ -205,6 +317,6 @@ const char* elpa_strerror(int code) {
   }
 }
 
-const char* elpa_hh_version(void) { return "elpa-hip 0.1 (gfx950)"; }
+const char* elpa_hh_version(void) { return "elpa-hip 0.2 (gfx950)"; }
 
 }  // extern "C"

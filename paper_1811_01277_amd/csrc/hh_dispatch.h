@@ -4,20 +4,33 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <vector>
+
 #include "../../include/elpa_hh.h"
 
 namespace ehh {
 
-// S = chase steps per tile of the diagonal schedule (0 = library choice)
+// Tiling of the diagonal launch schedule: steps = chase steps per tile
+// (0 = library choice); xcd = number of consecutive-tile groups the workgroup
+// ids are dealt to round robin (1 = linear order, 8 = one group per XCD);
+// streams = stripe groups run as separate launch sequences on concurrent
+// streams (1 = the caller's stream only).
+struct TileOpts {
+  int64_t steps;
+  int xcd;
+  int streams;
+};
+
 using StripeLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
-                                    int64_t n, int64_t nev, int64_t S, hipStream_t st,
+                                    int64_t n, int64_t nev, TileOpts opt, hipStream_t st,
                                     int num_cu);
 using BatchedLaunch = hipError_t (*)(const elpa_hh_problem* probs, const int64_t* idx,
-                                     int64_t cnt, int64_t S, hipStream_t st, int num_cu);
+                                     int64_t cnt, TileOpts opt, hipStream_t st, int num_cu);
 using RefLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
                                  int64_t n, int64_t nev, int64_t nb, hipStream_t st);
 
 struct StripeEntry {
+  int path;   // ELPA_PATH_STRIPE or ELPA_PATH_SPLIT
   int dtype;
   int nb;
   int k;
@@ -26,7 +39,73 @@ struct StripeEntry {
   BatchedLaunch batched;
 };
 
-const StripeEntry* stripe_table(int* size);
+const StripeEntry* stripe_table(int* size);  // one lane per column
+const StripeEntry* split_table(int* size);   // two lanes per column, packed reflectors
 RefLaunch ref_launcher(int dtype);
+
+// Timing of the main kernel sequence (the tile launches of the stripe paths,
+// the single launch of the reference path) of the latest call made on the
+// calling host thread, while enabled with elpa_hh_profile_enable: an event
+// pair around the whole sequence on the caller's stream, and one around every
+// launch on the stream it is launched on.
+struct ProfState {
+  bool on = false;
+  int dev = -1;
+  hipEvent_t a = nullptr, b = nullptr;
+  std::vector<hipEvent_t> ev;  // per launch: before, after
+  bool started = false, recorded = false;
+  int64_t launches = 0;
+  int path = 0, k = 0, streams = 1;
+  int64_t steps = 0;
+};
+ProfState& prof_state();  // thread-local
+
+// Brackets one launch sequence on `st`: an event before the first sequence of
+// a call, an event after every sequence (the last one counts), and before() /
+// after() around each launch.
+class ProfScope {
+ public:
+  ProfScope(hipStream_t st, int k, int64_t steps, int streams = 1) : st_(st) {
+    ProfState& p = prof_state();
+    int dev = -1;
+    on_ = p.on && p.a && (hipGetDevice(&dev) == hipSuccess) && dev == p.dev;
+    if (!on_) return;
+    if (!p.started && hipEventRecord(p.a, st) == hipSuccess) p.started = true;
+    p.k = k;
+    p.steps = steps;
+    p.streams = streams;
+  }
+  void before(hipStream_t s) {
+    if (!on_) return;
+    ProfState& p = prof_state();
+    const size_t i = 2 * (size_t)p.launches;
+    while (p.ev.size() < i + 2) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) {
+        on_ = false;
+        return;
+      }
+      p.ev.push_back(e);
+    }
+    (void)hipEventRecord(p.ev[i], s);
+  }
+  void after(hipStream_t s) {
+    if (!on_) return;
+    ProfState& p = prof_state();
+    (void)hipEventRecord(p.ev[2 * (size_t)p.launches + 1], s);
+    ++p.launches;
+  }
+  void end() {
+    if (!on_) return;
+    ProfState& p = prof_state();
+    if (hipEventRecord(p.b, st_) == hipSuccess) p.recorded = p.started;
+    on_ = false;
+  }
+  ~ProfScope() { end(); }
+
+ private:
+  hipStream_t st_;
+  bool on_ = false;
+};
 
 }  // namespace ehh

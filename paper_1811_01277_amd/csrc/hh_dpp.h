@@ -67,4 +67,111 @@ __device__ __forceinline__ void dpp_upd2(double& x0, double& x1, double V0, doub
                : "v"(V0), "v"(V1), "v"(nw), "i"(I));
 }
 
+// ---------------------------------------------------------------------------
+// Split-window blocks (two lanes per column, rows interleaved by parity).
+// A reflector's values for one lane half arrive as 16-value segments held in
+// VGPR pairs (lane 16r+i holds segment value i); each block below covers
+// broadcast lanes l0..l7 of one or two segments, so a reflector takes two
+// blocks per pass and one s_nop per 8 or 16 FMAs.  The _X forms add the
+// extra term of an odd window offset: segment 2's lane-0 value against one
+// more window row.
+// ---------------------------------------------------------------------------
+#define EHH_F(D, S, X, L) \
+  "v_fmac_f64_dpp %" #D ", %" #S ", %" #X " row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n"
+#define EHH_X(m, ...) m(__VA_ARGS__)
+#define EHH_LA 0, 1, 2, 3, 4, 5, 6, 7
+#define EHH_LB 8, 9, 10, 11, 12, 13, 14, 15
+#define EHH_VX8(p) \
+  "v"(p[0]), "v"(p[1]), "v"(p[2]), "v"(p[3]), "v"(p[4]), "v"(p[5]), "v"(p[6]), "v"(p[7])
+#define EHH_PX8(p)                                                                        \
+  "+v"(p[0]), "+v"(p[1]), "+v"(p[2]), "+v"(p[3]), "+v"(p[4]), "+v"(p[5]), "+v"(p[6]), \
+      "+v"(p[7])
+
+// one segment: a0/a1 += bcast(V0, l) * x  (%0 a0, %1 a1, %2 V0, %3..%10 x)
+#define EHH_SDOT1(l0, l1, l2, l3, l4, l5, l6, l7)                                      \
+  EHH_F(0, 2, 3, l0) EHH_F(1, 2, 4, l1) EHH_F(0, 2, 5, l2) EHH_F(1, 2, 6, l3)          \
+  EHH_F(0, 2, 7, l4) EHH_F(1, 2, 8, l5) EHH_F(0, 2, 9, l6) EHH_F(1, 2, 10, l7)
+// one segment: x += bcast(V, l) * nw  (%0..%7 x)
+#define EHH_SUPD1(V, NW, l0, l1, l2, l3, l4, l5, l6, l7)                                \
+  EHH_F(0, V, NW, l0) EHH_F(1, V, NW, l1) EHH_F(2, V, NW, l2) EHH_F(3, V, NW, l3)      \
+  EHH_F(4, V, NW, l4) EHH_F(5, V, NW, l5) EHH_F(6, V, NW, l6) EHH_F(7, V, NW, l7)
+// two segments: a0 += bcast(V0, l) * x, a1 += bcast(V1, l) * y
+// (%0 a0, %1 a1, %2 V0, %3 V1, %4..%11 x, %12..%19 y)
+#define EHH_SDOT2(l0, l1, l2, l3, l4, l5, l6, l7)                                      \
+  EHH_F(0, 2, 4, l0) EHH_F(1, 3, 12, l0) EHH_F(0, 2, 5, l1) EHH_F(1, 3, 13, l1)        \
+  EHH_F(0, 2, 6, l2) EHH_F(1, 3, 14, l2) EHH_F(0, 2, 7, l3) EHH_F(1, 3, 15, l3)        \
+  EHH_F(0, 2, 8, l4) EHH_F(1, 3, 16, l4) EHH_F(0, 2, 9, l5) EHH_F(1, 3, 17, l5)        \
+  EHH_F(0, 2, 10, l6) EHH_F(1, 3, 18, l6) EHH_F(0, 2, 11, l7) EHH_F(1, 3, 19, l7)
+// two segments: x += bcast(V0, l) * nw, y += bcast(V1, l) * nw (%0..%7 x, %8..%15 y)
+#define EHH_SUPD2(V0, V1, NW, l0, l1, l2, l3, l4, l5, l6, l7)                                 \
+  EHH_F(0, V0, NW, l0) EHH_F(8, V1, NW, l0) EHH_F(1, V0, NW, l1) EHH_F(9, V1, NW, l1)        \
+  EHH_F(2, V0, NW, l2) EHH_F(10, V1, NW, l2) EHH_F(3, V0, NW, l3) EHH_F(11, V1, NW, l3)      \
+  EHH_F(4, V0, NW, l4) EHH_F(12, V1, NW, l4) EHH_F(5, V0, NW, l5) EHH_F(13, V1, NW, l5)      \
+  EHH_F(6, V0, NW, l6) EHH_F(14, V1, NW, l6) EHH_F(7, V0, NW, l7) EHH_F(15, V1, NW, l7)
+
+// dot, one segment, lanes 0..7 and lanes 8..15 (+ extra term when EX)
+__device__ __forceinline__ void sdot1_a(double& a0, double& a1, double V0, const double* x) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_SDOT1, EHH_LA) : "+v"(a0), "+v"(a1) : "v"(V0), EHH_VX8(x));
+}
+template <bool EX>
+__device__ __forceinline__ void sdot1_b(double& a0, double& a1, double V0, double V2,
+                                        const double* x, const double* xe) {
+  if constexpr (EX)
+    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT1, EHH_LB) EHH_F(0, 11, 12, 0)
+                 : "+v"(a0), "+v"(a1)
+                 : "v"(V0), EHH_VX8(x), "v"(V2), "v"(xe[0]));
+  else
+    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT1, EHH_LB) : "+v"(a0), "+v"(a1) : "v"(V0), EHH_VX8(x));
+}
+// update, one segment
+__device__ __forceinline__ void supd1_a(double* x, double V0, double nw) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_SUPD1, 8, 9, EHH_LA) : EHH_PX8(x) : "v"(V0), "v"(nw));
+}
+template <bool EX>
+__device__ __forceinline__ void supd1_b(double* x, double* xe, double V0, double V2, double nw) {
+  if constexpr (EX)
+    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD1, 9, 10, EHH_LB) EHH_F(8, 11, 10, 0)
+                 : EHH_PX8(x), "+v"(xe[0])
+                 : "v"(V0), "v"(nw), "v"(V2));
+  else
+    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD1, 8, 9, EHH_LB) : EHH_PX8(x) : "v"(V0), "v"(nw));
+}
+// dot, two segments
+__device__ __forceinline__ void sdot2_a(double& a0, double& a1, double V0, double V1,
+                                        const double* x, const double* y) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_SDOT2, EHH_LA)
+               : "+v"(a0), "+v"(a1)
+               : "v"(V0), "v"(V1), EHH_VX8(x), EHH_VX8(y));
+}
+template <bool EX>
+__device__ __forceinline__ void sdot2_b(double& a0, double& a1, double V0, double V1, double V2,
+                                        const double* x, const double* y, const double* xe) {
+  if constexpr (EX)
+    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT2, EHH_LB) EHH_F(0, 20, 21, 0)
+                 : "+v"(a0), "+v"(a1)
+                 : "v"(V0), "v"(V1), EHH_VX8(x), EHH_VX8(y), "v"(V2), "v"(xe[0]));
+  else
+    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT2, EHH_LB)
+                 : "+v"(a0), "+v"(a1)
+                 : "v"(V0), "v"(V1), EHH_VX8(x), EHH_VX8(y));
+}
+// update, two segments
+__device__ __forceinline__ void supd2_a(double* x, double* y, double V0, double V1, double nw) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 16, 17, 18, EHH_LA)
+               : EHH_PX8(x), EHH_PX8(y)
+               : "v"(V0), "v"(V1), "v"(nw));
+}
+template <bool EX>
+__device__ __forceinline__ void supd2_b(double* x, double* y, double* xe, double V0, double V1,
+                                        double V2, double nw) {
+  if constexpr (EX)
+    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 17, 18, 19, EHH_LB) EHH_F(16, 20, 19, 0)
+                 : EHH_PX8(x), EHH_PX8(y), "+v"(xe[0])
+                 : "v"(V0), "v"(V1), "v"(nw), "v"(V2));
+  else
+    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 16, 17, 18, EHH_LB)
+                 : EHH_PX8(x), EHH_PX8(y)
+                 : "v"(V0), "v"(V1), "v"(nw));
+}
+
 }  // namespace ehh

@@ -44,12 +44,7 @@
 #include "hh_common.h"
 #include "hh_dispatch.h"
 #include "hh_dpp.h"
-
-#include <algorithm>
-#include <cstring>
-#include <mutex>
-#include <type_traits>
-#include <vector>
+#include "hh_sched.h"
 
 namespace ehh {
 
@@ -83,43 +78,6 @@ __global__ __launch_bounds__(64) void k_ref(const E* __restrict__ hh, const E* _
 }
 
 
-// Geometry of one problem of the stripe path (device copy used by the
-// batched kernels).
-struct ProblemDesc {
-  const void* hh;
-  const void* tau;
-  void* Q;
-  void* Qs;
-  int64_t n, nev, ldq, rows_pad;
-  int G, M, S;
-  int tile0;   // first 64x64 conversion tile of this problem (rows_pad/64 * G tiles)
-  int otile0;  // first conversion tile back (ceil(n/64) * G tiles)
-  int pad;
-};
-
-// One launch's share of one problem in the batched diagonal schedule:
-// blocks [m0, m0 + mcount) of problem p, every stripe; tiles [tile0,
-// tile0 + mcount*G) of the launch.
-struct DiagEntry {
-  int p;
-  int m0;
-  int mcount;
-  int tile0;
-};
-
-// index i with key(d[i]) <= key < key(d[i+1]) (d sorted by key)
-template <typename T, int T::*F>
-__device__ __forceinline__ int find_by(const T* __restrict__ d, int count, int key) {
-  int lo = 0, hi = count - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (d[mid].*F <= key)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
 
 template <typename E>
 __device__ __forceinline__ void to_rows_tile(const E* __restrict__ Q, int64_t ldq, int64_t n,
@@ -165,8 +123,8 @@ __global__ __launch_bounds__(256) void k_to_rows_b(const ProblemDesc* __restrict
   const int p = find_by<ProblemDesc, &ProblemDesc::tile0>(d, count, t);
   const ProblemDesc& P = d[p];
   const int local = t - P.tile0;
-  to_rows_tile<E>((const E*)P.Q, P.ldq, P.n, P.nev, (E*)P.Qs, P.rows_pad, local / P.G,
-                  local % P.G, tile);
+  to_rows_tile<E>((const E*)P.Q, P.ldq, P.n, P.nev, (E*)P.Qs, P.rows_pad, local / P.GT,
+                  local % P.GT, tile);
 }
 
 template <typename E>
@@ -177,8 +135,8 @@ __global__ __launch_bounds__(256) void k_from_rows_b(const ProblemDesc* __restri
   const int p = find_by<ProblemDesc, &ProblemDesc::otile0>(d, count, t);
   const ProblemDesc& P = d[p];
   const int local = t - P.otile0;
-  from_rows_tile<E>((const E*)P.Qs, P.rows_pad, (E*)P.Q, P.ldq, P.n, P.nev, local / P.G,
-                    local % P.G, tile);
+  from_rows_tile<E>((const E*)P.Qs, P.rows_pad, (E*)P.Q, P.ldq, P.n, P.nev, local / P.GT,
+                    local % P.GT, tile);
 }
 
 // ---------------------------------------------------------------------------
@@ -231,17 +189,6 @@ __device__ __forceinline__ Chunk<E, CH> load_chunk(const E* __restrict__ p) {
   return c;
 }
 
-__device__ __forceinline__ int zero_after(double d) {
-  int z;
-  asm("s_mov_b32 %0, 0" : "=s"(z) : "v"(d));
-  return z;
-}
-__device__ __forceinline__ int zero_after(float d) {
-  int z;
-  asm("s_mov_b32 %0, 0" : "=s"(z) : "v"(d));
-  return z;
-}
-__device__ __forceinline__ int zero_after(z64 d) { return zero_after(d.re); }
 
 template <typename E, typename D>
 __device__ __forceinline__ const E* after(const E* p, D dep) {
@@ -291,33 +238,6 @@ __device__ __forceinline__ void apply_reflector(E (&x)[W], int o, const E* __res
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Compile-time loop o = N-1, N-2, ..., 0 (every body gets a constant o, so
-// the window indices stay static without relying on the unroller's budget).
-template <int N>
-struct RevFor {
-  template <typename F>
-  static __device__ __forceinline__ void run(F&& f) {
-    f(std::integral_constant<int, N - 1>{});
-    RevFor<N - 1>::run(f);
-  }
-};
-template <>
-struct RevFor<0> {
-  template <typename F>
-  static __device__ __forceinline__ void run(F&&) {}
-};
-
-// Compile-time loop i = 0, 1, ..., N-1.
-template <int N, int I = 0>
-struct FwdFor {
-  template <typename F>
-  static __device__ __forceinline__ void run(F&& f) {
-    if constexpr (I < N) {
-      f(std::integral_constant<int, I>{});
-      FwdFor<N, I + 1>::run(f);
-    }
-  }
-};
 
 // ---------------------------------------------------------------------------
 // One chase step of one block: apply the K reflectors (s0+o, j), o = K-1..0,
@@ -485,10 +405,10 @@ template <typename E, int NB, int K, int OCC>
 __global__ __launch_bounds__(64, OCC) void k_diag(const E* __restrict__ hh,
                                                   const E* __restrict__ hh2,
                                                   const E* __restrict__ tau, E* __restrict__ Qs,
-                                                  int64_t rows_pad, int64_t n, int G, int M,
-                                                  int t, int m0, int S) {
-  const int b = (int)blockIdx.x;
-  const int c = b % G;
+                                                  int64_t rows_pad, int64_t n, int c0, int G,
+                                                  int M, int t, int m0, int S, int xcd) {
+  const int b = tile_of((int)blockIdx.x, (int)gridDim.x, xcd);
+  const int c = c0 + b % G;
   const int m = m0 + b / G;
   const int q = t - (M - 1 - m);
   run_tile<E, NB, K>(hh, hh2, tau, Qs, rows_pad, n, c, m, q, S);
@@ -497,8 +417,8 @@ __global__ __launch_bounds__(64, OCC) void k_diag(const E* __restrict__ hh,
 template <typename E, int NB, int K, int OCC>
 __global__ __launch_bounds__(64, OCC) void k_diag_b(const ProblemDesc* __restrict__ d,
                                                     const DiagEntry* __restrict__ e, int ecount,
-                                                    int t) {
-  const int b = (int)blockIdx.x;
+                                                    int t, int xcd) {
+  const int b = tile_of((int)blockIdx.x, (int)gridDim.x, xcd);
   const int ei = find_by<DiagEntry, &DiagEntry::tile0>(e, ecount, b);
   const DiagEntry& E0 = e[ei];
   const ProblemDesc& P = d[E0.p];
@@ -522,117 +442,12 @@ hipError_t launch_ref(const void* hh, const void* tau, void* Q, int64_t ldq, int
   return hipGetLastError();
 }
 
-inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
-
-// Stream-ordered host->device upload of small host tables.  hipMemcpyAsync
-// from pageable memory copies at call time, but a destination obtained from
-// hipMallocAsync is only valid in stream order (earlier work on the stream may
-// still use the recycled memory), so tables are staged in pinned host buffers
-// and copied asynchronously; a buffer is reused only after the event recorded
-// behind its copy has completed.  One pool per device.
-class PinnedStaging {
- public:
-  static PinnedStaging& for_device(int dev) {
-    static std::mutex mu;
-    static std::vector<PinnedStaging*> pools;
-    std::lock_guard<std::mutex> g(mu);
-    if (dev < 0) dev = 0;
-    if ((size_t)dev >= pools.size()) pools.resize((size_t)dev + 1, nullptr);
-    if (!pools[(size_t)dev]) pools[(size_t)dev] = new PinnedStaging();
-    return *pools[(size_t)dev];
-  }
-
-  // copy `bytes` from host `src` to device `dst` in stream order on `st`
-  hipError_t upload(void* dst, const void* src, size_t bytes, hipStream_t st) {
-    if (bytes == 0) return hipSuccess;
-    std::lock_guard<std::mutex> g(mu_);
-    Buf* b = nullptr;
-    for (Buf& x : bufs_) {
-      if (x.cap >= bytes && hipEventQuery(x.ev) == hipSuccess) {
-        b = &x;
-        break;
-      }
-    }
-    if (!b) {
-      Buf nb{};
-      nb.cap = std::max<size_t>(bytes, 1 << 16);
-      hipError_t e = hipHostMalloc(&nb.p, nb.cap, hipHostMallocDefault);
-      if (e != hipSuccess) return e;
-      e = hipEventCreateWithFlags(&nb.ev, hipEventDisableTiming);
-      if (e != hipSuccess) {
-        (void)hipHostFree(nb.p);
-        return e;
-      }
-      bufs_.push_back(nb);
-      b = &bufs_.back();
-    }
-    std::memcpy(b->p, src, bytes);
-    hipError_t e = hipMemcpyAsync(dst, b->p, bytes, hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    return hipEventRecord(b->ev, st);
-  }
-
- private:
-  struct Buf {
-    void* p;
-    size_t cap;
-    hipEvent_t ev;
-  };
-  std::mutex mu_;
-  std::vector<Buf> bufs_;
-};
-
-// Host-side geometry and diagonal schedule of one problem.
-struct DiagPlan {
-  int64_t n = 0, nev = 0, NB = 0, K = 0, S = 1;
-  int64_t G = 0, M = 0, rows_pad = 0, T = 0;
-  std::vector<int> Qm;  // groups of block m
-
-  DiagPlan(int64_t n_, int64_t nev_, int64_t NB_, int64_t K_, int64_t S_)
-      : n(n_), nev(nev_), NB(NB_), K(K_), S(S_) {
-    G = (nev + 63) / 64;
-    M = (n - 1 + K - 1) / K;
-    // deepest row touched: s0 + 1 + (J0-1)*NB + W - 1 < n + NB + K
-    rows_pad = ((n + NB + K + 63) / 64) * 64;
-    Qm.resize((size_t)M);
-    T = 0;
-    for (int64_t m = 0; m < M; ++m) {
-      const int64_t J0 = (n - 1 - m * K + NB - 1) / NB;
-      Qm[(size_t)m] = (int)((J0 + S - 1) / S);
-      T = std::max(T, (M - 1 - m) + Qm[(size_t)m]);
-    }
-  }
-  // blocks active at launch t: [m0, m0 + cnt)
-  void active(int64_t t, int64_t* m0, int64_t* cnt) const {
-    int64_t a = M - 1 - t;
-    if (a < 0) a = 0;
-    int64_t b = a;
-    while (b < M && t - (M - 1 - b) < Qm[(size_t)b]) ++b;
-    *m0 = a;
-    *cnt = b - a;
-  }
-  template <typename E>
-  size_t qbytes() const {
-    return align256((size_t)rows_pad * (size_t)G * 64 * sizeof(E));
-  }
-};
-
-// Chase steps per tile: the largest S (fewest launches and window reloads)
-// that still gives the middle launches several waves per SIMD slot.
-inline int64_t choose_steps(int64_t n, int64_t nev, int64_t NB, int64_t K, int num_cu, int occ) {
-  const int64_t G = (nev + 63) / 64;
-  const int64_t M = (n - 1 + K - 1) / K;
-  const int64_t J = (n - 1 + NB - 1) / NB;
-  const int64_t slots = (int64_t)num_cu * 4 * occ;
-  int64_t S = 16;
-  while (S > 1 && G * std::min(M, (J + S - 1) / S) < 4 * slots) S /= 2;
-  return S;
-}
 
 template <typename E, int NB, int K, int OCC>
 hipError_t launch_diag(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
-                       int64_t nev, int64_t S, hipStream_t st, int num_cu) {
-  if (S <= 0) S = choose_steps(n, nev, NB, K, num_cu, OCC);
+                       int64_t nev, TileOpts opt, hipStream_t st, int num_cu) {
+  static const int64_t slots = wave_slots(k_diag<E, NB, K, OCC>, num_cu);
+  const int64_t S = opt.steps > 0 ? opt.steps : choose_steps(n, nev, NB, K, slots, 64);
   const DiagPlan pl(n, nev, NB, K, S);
   if (pl.G * pl.M >= INT32_MAX || n + NB + K >= INT32_MAX) return hipErrorInvalidValue;
   E* Qs = nullptr;
@@ -640,13 +455,35 @@ hipError_t launch_diag(const void* hh, const void* tau, void* Q, int64_t ldq, in
   if (err != hipSuccess) return err;
   hipLaunchKernelGGL(k_to_rows<E>, dim3((unsigned)(pl.rows_pad / 64), (unsigned)pl.G), dim3(256),
                      0, st, (const E*)Q, ldq, n, nev, Qs, pl.rows_pad);
-  for (int64_t t = 0; t < pl.T; ++t) {
-    int64_t m0, cnt;
-    pl.active(t, &m0, &cnt);
-    if (cnt == 0) continue;
-    hipLaunchKernelGGL((k_diag<E, NB, K, OCC>), dim3((unsigned)(cnt * pl.G)), dim3(64), 0, st,
-                       (const E*)hh, (const E*)hh, (const E*)tau, Qs, pl.rows_pad, n, (int)pl.G,
-                       (int)pl.M, (int)t, (int)m0, (int)S);
+  const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(opt.streams, pl.G));
+  ProfScope prof(st, K, S, ns);
+  {
+    // stripe groups on concurrent streams (see the split kernel's launcher)
+    StreamFork fork(st, ns);
+    if (fork.error() != hipSuccess) {
+      (void)hipFreeAsync(Qs, st);
+      return fork.error();
+    }
+    for (int64_t t = 0; t < pl.T; ++t) {
+      int64_t m0, cnt;
+      pl.active(t, &m0, &cnt);
+      if (cnt == 0) continue;
+      for (int i = 0; i < ns; ++i) {
+        const int64_t c_lo = pl.G * i / ns, gs = pl.G * (i + 1) / ns - c_lo;
+        prof.before(fork.stream(i));
+        hipLaunchKernelGGL((k_diag<E, NB, K, OCC>), dim3((unsigned)(cnt * gs)), dim3(64), 0,
+                           fork.stream(i), (const E*)hh, (const E*)hh, (const E*)tau, Qs,
+                           pl.rows_pad, n, (int)c_lo, (int)gs, (int)pl.M, (int)t, (int)m0, (int)S,
+                           opt.xcd);
+        prof.after(fork.stream(i));
+      }
+    }
+    err = fork.join();
+  }
+  prof.end();
+  if (err != hipSuccess) {
+    (void)hipFreeAsync(Qs, st);
+    return err;
   }
   hipLaunchKernelGGL(k_from_rows<E>, dim3((unsigned)((n + 63) / 64), (unsigned)pl.G), dim3(256),
                      0, st, (const E*)Qs, pl.rows_pad, (E*)Q, ldq, n, nev);
@@ -660,7 +497,9 @@ hipError_t launch_diag(const void* hh, const void* tau, void* Q, int64_t ldq, in
 // problems run side by side, launch t holding launch t of every problem.
 template <typename E, int NB, int K, int OCC>
 hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
-                               int64_t S, hipStream_t st, int num_cu) {
+                               TileOpts opt, hipStream_t st, int num_cu) {
+  const int64_t S = opt.steps;
+  static const int64_t slots = wave_slots(k_diag_b<E, NB, K, OCC>, num_cu);
   std::vector<ProblemDesc> d;
   std::vector<DiagPlan> plans;
   d.reserve((size_t)cnt);
@@ -675,7 +514,7 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
     const elpa_hh_problem& p = probs[idx[i]];
     if (p.n <= 1 || p.nev == 0) continue;
     // all problems share the launch slots: size S from the batch's columns
-    const int64_t s = S > 0 ? S : choose_steps(p.n, total_cols, NB, K, num_cu, OCC);
+    const int64_t s = S > 0 ? S : choose_steps(p.n, total_cols, NB, K, slots, 64);
     plans.emplace_back(p.n, p.nev, NB, K, s);
     ProblemDesc x{};
     x.hh = p.hh;
@@ -693,6 +532,7 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
   for (size_t i = 0; i < d.size(); ++i) {
     const DiagPlan& pl = plans[i];
     d[i].G = (int)pl.G;
+    d[i].GT = (int)pl.G;  // 64-column stripes: one conversion tile column per stripe
     d[i].M = (int)pl.M;
     d[i].S = (int)pl.S;
     d[i].rows_pad = pl.rows_pad;
@@ -743,20 +583,25 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
   const DiagEntry* de = (const DiagEntry*)(ws + dbytes);
   const int count = (int)d.size();
   hipLaunchKernelGGL(k_to_rows_b<E>, dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
+  ProfScope prof(st, K, S);
   for (int64_t t = 0; t < T; ++t) {
     const int64_t ne = eoff[(size_t)t + 1] - eoff[(size_t)t];
     if (ne == 0) continue;
+    prof.before(st);
     hipLaunchKernelGGL((k_diag_b<E, NB, K, OCC>), dim3((unsigned)etiles[(size_t)t]), dim3(64), 0,
-                       st, dd, de + eoff[(size_t)t], (int)ne, (int)t);
+                       st, dd, de + eoff[(size_t)t], (int)ne, (int)t, opt.xcd);
+    prof.after(st);
   }
+  prof.end();
   hipLaunchKernelGGL(k_from_rows_b<E>, dim3((unsigned)otiles), dim3(256), 0, st, dd, count);
   err = hipGetLastError();
   const hipError_t e2 = hipFreeAsync(ws, st);
   return err != hipSuccess ? err : e2;
 }
 
-#define EHH_DIAG(E, DT, NB, K, OCC) \
-  {DT, NB, K, OCC, &launch_diag<E, NB, K, OCC>, &launch_diag_batched<E, NB, K, OCC>}
+#define EHH_DIAG(E, DT, NB, K, OCC)                                                    \
+  {ELPA_PATH_STRIPE, DT, NB, K, OCC, &launch_diag<E, NB, K, OCC>,                        \
+   &launch_diag_batched<E, NB, K, OCC>}
 
 const StripeEntry* stripe_table(int* size) {
   static const StripeEntry table[] = {

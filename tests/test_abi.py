@@ -110,4 +110,26 @@ def test_plan_support_table():
     assert P.plan_supported(5, P.R64, P.PATH_AUTO)
     assert not P.plan_supported(5, P.R64, P.PATH_STRIPE, 4)
     assert not P.plan_supported(64, 9, P.PATH_AUTO)
+    # two-lane kernel: real fp64, nbw 32 / 64, even k
+    for nbw, k in [(64, 48), (64, 64), (64, 80), (32, 32), (32, 64), (32, 96)]:
+        assert P.plan_supported(nbw, P.R64, P.PATH_SPLIT, k), (nbw, k)
+    assert P.plan_supported(64, P.R64, P.PATH_SPLIT)          # library default k
+    assert not P.plan_supported(64, P.R32, P.PATH_SPLIT, 64)
+    assert not P.plan_supported(64, P.C64, P.PATH_SPLIT)
+    assert not P.plan_supported(64, P.R64, P.PATH_SPLIT, 63)
+    assert not P.plan_supported(16, P.R64, P.PATH_SPLIT)
+    assert not P.plan_supported(64, P.R64, 4)                # no such path
+    rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 3)   # unknown order
+    assert rc == -6
+    rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 0, 9)  # > 8 streams
+    assert rc == -6
+    pl = P.binding._Plan(0, 0, 0, 0, 0, 1)                                  # reserved != 0
+    assert P.library().elpa_hh_trafo_plan(10, 5, 2, 8, 8, 8, 10, P.R64, None, C.byref(pl)) == -6
+
+
+def test_profile_api_without_calls():
+    P.profile_enable(False)
+    with pytest.raises(P.ElpaError) as e:
+        P.profile_last()                  # nothing recorded
+    assert e.value.code == -1
     assert P.strerror(12345) == "unknown error code"

@@ -19,7 +19,8 @@ from oracle import bt, checks, solve
 pytestmark = pytest.mark.gpu
 
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
-KS = [1, 2, 4, 6, 8, 16, 24, 32, 48, 64]
+KS = [1, 2, 4, 6, 8, 16, 24, 32, 40, 48, 64]
+SPLIT_KS = [32, 48, 64, 80, 96]
 
 
 @pytest.fixture(scope="module")
@@ -53,12 +54,13 @@ def upload_q(torch, dev, Z, dt, ldq=None):
     return buf, buf[:, :n].t()
 
 
-def run_gpu(torch, dev, hh, tau, Z, nbw, dt, path=None, k=0, ldq=None):
+def run_gpu(torch, dev, hh, tau, Z, nbw, dt, path=None, k=0, ldq=None, steps=0, order=0,
+            streams=0):
     import paper_1811_01277_amd as P
     buf, q = upload_q(torch, dev, Z, dt, ldq)
     h = torch.from_numpy(hh.astype(npdtype(dt))).to(dev)
     t = torch.from_numpy(tau.astype(npdtype(dt))).to(dev)
-    P.hh_trafo(q, h, t, nbw, path=path, k=k)
+    P.hh_trafo(q, h, t, nbw, path=path, k=k, steps=steps, order=order, streams=streams)
     torch.cuda.synchronize()
     return buf.cpu().numpy().T  # (ldq, nev)
 
@@ -88,6 +90,7 @@ def plans(nbw, dt):
     code = {"r64": P.R64, "r32": P.R32, "c64": P.C64}[dt]
     out = [(None, 0), (P.PATH_REF, 0)]
     out += [(P.PATH_STRIPE, k) for k in KS if P.plan_supported(nbw, code, P.PATH_STRIPE, k)]
+    out += [(P.PATH_SPLIT, k) for k in SPLIT_KS if P.plan_supported(nbw, code, P.PATH_SPLIT, k)]
     return out
 
 
@@ -136,6 +139,92 @@ def test_padding_rows_untouched_and_replay_bitwise(torch_dev, dt):
     assert checks.max_rel_err(a[:n], ref) <= TOL[dt]
 
 
+@pytest.mark.parametrize("nbw,k", [(64, 48), (64, 64), (64, 80), (32, 32), (32, 64), (32, 96)])
+def test_split_steps_per_tile(torch_dev, nbw, k):
+    """Two-lane kernel with tiles of 1, 3 and 16 chase steps: group
+    boundaries inside a block (carried rows written back and reloaded), the
+    last group of a block shorter than the others, n - 1 not a multiple of k."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nev = 1000, 97
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "r64", 51 + k)
+    ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
+    outs = []
+    for steps in (1, 3, 16):
+        print(f"split n={n} nbw={nbw} k={k} steps={steps}", flush=True)
+        got = run_gpu(torch, dev, hh, tau, Z, nbw, "r64", P.PATH_SPLIT, k, steps=steps)
+        assert checks.max_rel_err(got, ref) <= TOL["r64"], steps
+        outs.append(got)
+    # the tiling changes only which wave runs a step, not the arithmetic
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("dt,path,k", [("r64", 3, 64), ("r64", 2, 32), ("r32", 2, 32),
+                                       ("c64", 2, 4)])
+def test_tile_order_does_not_change_results(torch_dev, dt, path, k):
+    """Linear and die-grouped tile orders run the same tiles: bitwise equal."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 900, 64, 333
+    hh, tau, Z = oracle_inputs(n, nbw, nev, dt, 71)
+    ref = bt.bt_tridiag_to_band(rounded(hh, dt), rounded(tau, dt), rounded(Z, dt), n, nbw)
+    got = [run_gpu(torch, dev, hh, tau, Z, nbw, dt, path, k, steps=2, order=o)
+           for o in (P.ORDER_LINEAR, P.ORDER_XCD)]
+    assert np.array_equal(got[0], got[1])
+    assert checks.max_rel_err(got[0], ref) <= TOL[dt]
+
+
+def test_stripe_groups_on_streams(torch_dev):
+    """Stripe groups on 2, 3 and 8 library streams (more groups than
+    stripes is clamped): bitwise equal to one stream, and the caller's stream
+    is ordered behind all groups (the result is read right after the call)."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 800, 64, 161   # 6 stripes of 32 columns, the last one ragged
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "r64", 81)
+    ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
+    one = run_gpu(torch, dev, hh, tau, Z, nbw, "r64", P.PATH_SPLIT, 64, steps=3, streams=1)
+    assert checks.max_rel_err(one, ref) <= TOL["r64"]
+    P.profile_enable(True)
+    try:
+        for ns in (2, 3, 8):
+            print(f"streams={ns}", flush=True)
+            got = run_gpu(torch, dev, hh, tau, Z, nbw, "r64", P.PATH_SPLIT, 64, steps=3,
+                          streams=ns)
+            assert np.array_equal(got, one), ns
+            pr = P.profile_last()
+            M, J0 = -(-(n - 1) // 64), -(-(n - 1) // nbw)
+            assert pr["launches"] == min(ns, 6) * (M + -(-J0 // 3) - 1)
+    finally:
+        P.profile_enable(False)
+
+
+def test_profile_reports_main_kernel_sequence(torch_dev):
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 700, 64, 300
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "r64", 61)
+    P.profile_enable(True)
+    try:
+        run_gpu(torch, dev, hh, tau, Z, nbw, "r64", P.PATH_SPLIT, 64, steps=2, streams=1)
+        a = P.profile_last()
+        run_gpu(torch, dev, hh, tau, Z, nbw, "r64", P.PATH_SPLIT, 64, steps=2)
+        a2 = P.profile_last()   # library default: two stripe groups
+        run_gpu(torch, dev, hh, tau, Z, nbw, "r64", P.PATH_REF)
+        b = P.profile_last()
+    finally:
+        P.profile_enable(False)
+    # diagonal schedule: M + ceil(J0 / steps) - 1 launches (M = ceil((n-1)/k) blocks)
+    M, J0 = -(-(n - 1) // 64), -(-(n - 1) // nbw)
+    assert a["path"] == P.PATH_SPLIT and a["k"] == 64 and a["steps"] == 2
+    assert a["launches"] == M + -(-J0 // 2) - 1 and a["kernel_ms"] > 0 and a["streams"] == 1
+    assert 0 < a["sum_launch_ms"] <= a["kernel_ms"] * 1.01
+    assert a2["streams"] == 2 and a2["launches"] == 2 * a["launches"]
+    assert b["path"] == P.PATH_REF and b["launches"] == 1 and b["kernel_ms"] > 0
+    with pytest.raises(P.ElpaError):
+        P.profile_last()
+
+
 def test_column_independence_nan_isolation_identity(torch_dev):
     torch, dev = torch_dev
     n, nbw, nev = 260, 64, 140
@@ -171,30 +260,35 @@ def test_error_leaves_q_untouched(torch_dev):
 
 
 def sampled_columns(nev):
-    cols = {0, 1, 63, 64, nev // 2, nev - 1}
+    cols = {0, 1, 31, 32, 63, 64, nev // 2, nev - 1}
     return sorted(c for c in cols if 0 <= c < nev)
 
 
 FULL = [
-    (8192, 64, 819, "r64"), (8192, 64, 4096, "r64"),
-    (20000, 64, 2000, "r64"), (20000, 64, 10000, "r64"), (20000, 64, 20000, "r64"),
-    (20000, 64, 2000, "r32"), (20000, 64, 2000, "c64"),
+    # (n, nbw, nev, dtype, plan (path, k) or None for the library choice)
+    (8192, 64, 819, "r64", None), (8192, 64, 4096, "r64", None),
+    (20000, 64, 2000, "r64", None), (20000, 64, 10000, "r64", None),
+    (20000, 64, 20000, "r64", None),
+    (20000, 64, 2000, "r64", (2, 32)),   # one-lane stripe kernel at full size
+    (20000, 64, 2000, "r32", None), (20000, 64, 2000, "c64", None),
 ]
 
 
-@pytest.mark.parametrize("case", FULL, ids=[f"n{c[0]}_e{c[2]}_{c[3]}" for c in FULL])
+@pytest.mark.parametrize("case", FULL, ids=[f"n{c[0]}_e{c[2]}_{c[3]}" + (
+    f"_p{c[4][0]}k{c[4][1]}" if c[4] else "") for c in FULL])
 def test_parity_full_size_sampled(torch_dev, case):
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
-    n, nbw, nev, dt = case
+    n, nbw, nev, dt, plan = case
+    path, k = plan if plan else (None, 0)
     cplx = dt == "c64"
     hh, tau = W.synthetic_reflectors(n, nbw, complex_=cplx, seed=n + nev)
     Z = W.gaussian_block(n, nev, complex_=cplx, seed=n + nev + 1)
-    print(f"full case n={n} nev={nev} dt={dt}", flush=True)
+    print(f"full case n={n} nev={nev} dt={dt} plan={plan}", flush=True)
     q = torch.from_numpy(np.ascontiguousarray(Z.T).astype(npdtype(dt))).to(dev).t()
     h = torch.from_numpy(hh.astype(npdtype(dt))).to(dev)
     t = torch.from_numpy(tau.astype(npdtype(dt))).to(dev)
-    P.hh_trafo(q, h, t, nbw)
+    P.hh_trafo(q, h, t, nbw, path=path, k=k)
     torch.cuda.synchronize()
     cols = sampled_columns(nev)
     got = q[:, cols].cpu().numpy()
