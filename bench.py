@@ -53,6 +53,25 @@ def parse():
     return ap.parse_args()
 
 
+def recorded_traffic(workload):
+    """HBM bytes per launch of the dominant kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (profiles/*_traffic.json), if they were taken
+    for this workload and plan with the kernel sources as they are now; else
+    None."""
+    import glob
+    import hashlib
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.json"))):
+        side = json.load(open(f))
+        if side.get("workload") != workload:
+            continue
+        h = hashlib.sha256()
+        for src in side["kernel_sources"]:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest() == side["kernel_sources_sha256"]:
+            return side["bytes_per_launch"]
+    return None
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size (read mib MiB, write mib MiB).
     Under rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE its counters give the factor
@@ -173,6 +192,9 @@ def main():
     achieved = (flops / launches) / (avg_launch_ms * 1e-3) * in_flight / 1e12
     peak = PEAK_TFLOPS[dt]
     kname = {1: "k_ref", 2: "k_diag", 3: "k_split"}.get(prof["path"], "?")
+    traffic = recorded_traffic({"n": n, "nbw": nbw, "nev": nev, "dtype": dt, "path": prof["path"],
+                                "k": prof["k"], "tile_steps": prof["steps"],
+                                "streams": prof["streams"]})
     value = flops / (ms * 1e-3) / 1e9
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
@@ -185,7 +207,8 @@ def main():
                             "streams": prof["streams"]}},
         "pct_fp64_peak": round(100.0 * achieved / PEAK_TFLOPS["r64"], 2),
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
+                     "traffic": None if traffic is None else round(traffic),
                      "kernel": kname, "launches": prof["launches"],
                      "avg_launch_us": round(avg_launch_ms * 1e3, 2),
                      "launches_in_flight": round(in_flight, 3),

@@ -517,7 +517,9 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
 const StripeEntry* split_table(int* size) {
   static const StripeEntry table[] = {
       EHH_SPLIT(32, 32, 2, 2), EHH_SPLIT(32, 64, 2, 2), EHH_SPLIT(32, 96, 2, 2),
-      EHH_SPLIT(64, 48, 2, 2), EHH_SPLIT(64, 64, 2, 2), EHH_SPLIT(64, 80, 2, 2),
+      // k = 48 and 64 fit three waves per SIMD, k = 80 two (with the values of three
+      // reflectors in flight)
+      EHH_SPLIT(64, 48, 2, 4), EHH_SPLIT(64, 64, 2, 2), EHH_SPLIT(64, 80, 2, 3),
   };
   *size = (int)(sizeof(table) / sizeof(table[0]));
   return table;
