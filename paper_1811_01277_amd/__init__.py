@@ -9,8 +9,8 @@ There is no CPU fallback: if the library is missing, import of the binding
 functions raises.
 """
 from .binding import (  # noqa: F401
-    C64, ORDER_AUTO, ORDER_LINEAR, ORDER_XCD, PATH_AUTO, PATH_REF, PATH_SPLIT, PATH_STRIPE, R32,
-    R64, ElpaError, hh_trafo,
+    C64, ORDER_AUTO, ORDER_LINEAR, ORDER_XCD, PATH_AUTO, PATH_REF, PATH_SPLIT, PATH_STRIPE, PATH_WY,
+    R32, R64, ElpaError, hh_trafo,
     hh_trafo_batched, hh_trafo_ptr, library, library_path, num_reflectors, plan_supported,
     profile_enable, profile_last, slot_offset, strerror, version,
 )

@@ -6,7 +6,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_NAME = "libelpahip.so"
 
 R64, R32, C64 = 0, 1, 2
-PATH_AUTO, PATH_REF, PATH_STRIPE, PATH_SPLIT = 0, 1, 2, 3
+PATH_AUTO, PATH_REF, PATH_STRIPE, PATH_SPLIT, PATH_WY = 0, 1, 2, 3, 4
 ORDER_AUTO, ORDER_LINEAR, ORDER_XCD = 0, 1, 2
 
 _lib = None

@@ -25,8 +25,9 @@ int64_t elem_size(int32_t dtype) {
 
 const ehh::StripeEntry* find_entry(int path, int32_t dtype, int64_t nb, int k) {
   int cnt = 0;
-  const ehh::StripeEntry* tab =
-      path == ELPA_PATH_SPLIT ? ehh::split_table(&cnt) : ehh::stripe_table(&cnt);
+  const ehh::StripeEntry* tab = path == ELPA_PATH_SPLIT ? ehh::split_table(&cnt)
+                                : path == ELPA_PATH_WY  ? ehh::wy_table(&cnt)
+                                                        : ehh::stripe_table(&cnt);
   for (int i = 0; i < cnt; ++i) {
     const ehh::StripeEntry& e = tab[i];
     if (e.path == path && e.dtype == dtype && e.nb == nb && e.k == k) return &e;
@@ -38,10 +39,16 @@ const ehh::StripeEntry* find_entry(int path, int32_t dtype, int64_t nb, int k) {
 // compiled entry in order of preference (0 if none).
 int default_k(int path, int32_t dtype, int64_t nb) {
   static const int split_pref[] = {80, 64, 48, 32, 96};
+  static const int wy_pref[] = {64, 48, 32, 96};
   static const int stripe_pref[] = {32, 16, 8, 4};
   static const int stripe_pref_c[] = {4, 2};
   if (path == ELPA_PATH_SPLIT) {
     for (int k : split_pref)
+      if (find_entry(path, dtype, nb, k)) return k;
+    return 0;
+  }
+  if (path == ELPA_PATH_WY) {
+    for (int k : wy_pref)
       if (find_entry(path, dtype, nb, k)) return k;
     return 0;
   }
@@ -57,9 +64,10 @@ int default_k(int path, int32_t dtype, int64_t nb) {
 
 // Kernel that runs (dtype, nb) under `plan` (NULL = library choice).  Returns
 // the table entry, or nullptr with *path = ELPA_PATH_REF for the reference
-// kernel; *rc = ELPA_ERR_PLAN if an explicit plan cannot run.
+// kernel; *rc = ELPA_ERR_PLAN if an explicit plan cannot run.  batched: the
+// kernel must have a batched form (the library choice skips those without).
 const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* plan, int* path,
-                                int* rc) {
+                                int* rc, bool batched = false) {
   *rc = ELPA_OK;
   if (plan && (plan->order < ELPA_ORDER_AUTO || plan->order > ELPA_ORDER_XCD ||
                plan->streams < 0 || plan->streams > 8 || plan->reserved != 0)) {
@@ -72,10 +80,11 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
   switch (want) {
     case ELPA_PATH_REF: return nullptr;
     case ELPA_PATH_STRIPE:
-    case ELPA_PATH_SPLIT: {
+    case ELPA_PATH_SPLIT:
+    case ELPA_PATH_WY: {
       const int kk = k ? k : default_k(want, dtype, nb);
       const ehh::StripeEntry* e = kk ? find_entry(want, dtype, nb, kk) : nullptr;
-      if (!e) {
+      if (!e || (batched && !e->batched)) {
         *rc = ELPA_ERR_PLAN;
         return nullptr;
       }
@@ -83,10 +92,16 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
       return e;
     }
     case ELPA_PATH_AUTO: {
-      for (int fam : {ELPA_PATH_SPLIT, ELPA_PATH_STRIPE}) {
+      // fp64: two-lane VALU kernel; fp32: compact-WY on fp32 MFMA (twice the
+      // VALU rate); complex: one-lane VALU kernel
+      const int order32[] = {ELPA_PATH_WY, ELPA_PATH_STRIPE};
+      const int order[] = {ELPA_PATH_SPLIT, ELPA_PATH_STRIPE};
+      const int* fams = dtype == ELPA_R32 ? order32 : order;
+      for (int f = 0; f < 2; ++f) {
+        const int fam = fams[f];
         const int kk = k ? k : default_k(fam, dtype, nb);
         const ehh::StripeEntry* e = kk ? find_entry(fam, dtype, nb, kk) : nullptr;
-        if (e) {
+        if (e && !(batched && !e->batched)) {
           *path = fam;
           return e;
         }
@@ -208,7 +223,7 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
 int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* stream,
                           const elpa_hh_plan* plan) {
   if (count < 0 || (count > 0 && !probs)) return ELPA_ERR_ARG;
-  if (plan && (plan->path < ELPA_PATH_AUTO || plan->path > ELPA_PATH_SPLIT)) return ELPA_ERR_PLAN;
+  if (plan && (plan->path < ELPA_PATH_AUTO || plan->path > ELPA_PATH_WY)) return ELPA_ERR_PLAN;
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
     const int rc = validate(p.n, p.nev, p.nbw, p.hh, p.tau, p.Q, p.ldq, p.dtype);
@@ -223,7 +238,7 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
     int path = 0, rc = 0;
-    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, plan, &path, &rc);
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, plan, &path, &rc, true);
     if (rc != ELPA_OK) return rc;
     if (p.n <= 1 || p.nev == 0) continue;
     last_path = path;

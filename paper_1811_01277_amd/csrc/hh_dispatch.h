@@ -30,17 +30,18 @@ using RefLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64
                                  int64_t n, int64_t nev, int64_t nb, hipStream_t st);
 
 struct StripeEntry {
-  int path;   // ELPA_PATH_STRIPE or ELPA_PATH_SPLIT
+  int path;   // ELPA_PATH_STRIPE, ELPA_PATH_SPLIT or ELPA_PATH_WY
   int dtype;
   int nb;
   int k;
   int occ;  // waves per SIMD the kernel is compiled for
   StripeLaunch fn;
-  BatchedLaunch batched;
+  BatchedLaunch batched;  // null: no batched form
 };
 
 const StripeEntry* stripe_table(int* size);  // one lane per column
 const StripeEntry* split_table(int* size);   // two lanes per column, packed reflectors
+const StripeEntry* wy_table(int* size);      // compact-WY sub-groups on MFMA
 RefLaunch ref_launcher(int dtype);
 
 // Timing of the main kernel sequence (the tile launches of the stripe paths,

@@ -118,13 +118,26 @@ def test_plan_support_table():
     assert not P.plan_supported(64, P.C64, P.PATH_SPLIT)
     assert not P.plan_supported(64, P.R64, P.PATH_SPLIT, 63)
     assert not P.plan_supported(16, P.R64, P.PATH_SPLIT)
-    assert not P.plan_supported(64, P.R64, 4)                # no such path
+    assert not P.plan_supported(64, P.R64, 5)                # no such path
+    # compact-WY MFMA path: real fp64 / fp32, nbw 32 / 64, k a multiple of 16
+    for nbw, k, dt in [(64, 32, P.R64), (64, 64, P.R64), (32, 96, P.R64), (64, 64, P.R32)]:
+        assert P.plan_supported(nbw, dt, P.PATH_WY, k), (nbw, k, dt)
+    assert not P.plan_supported(64, P.C64, P.PATH_WY)
+    assert not P.plan_supported(64, P.R64, P.PATH_WY, 40)
     rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 3)   # unknown order
     assert rc == -6
     rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 0, 9)  # > 8 streams
     assert rc == -6
     pl = P.binding._Plan(0, 0, 0, 0, 0, 1)                                  # reserved != 0
     assert P.library().elpa_hh_trafo_plan(10, 5, 2, 8, 8, 8, 10, P.R64, None, C.byref(pl)) == -6
+
+
+def test_batched_rejects_family_without_batched_form():
+    # the WY path has no batched launcher: the whole call is refused up front
+    pr = (P.binding._Problem * 1)()
+    pr[0] = P.binding._Problem(100, 10, 64, 100, 8, 8, 8, P.R64, 0)
+    pl = P.binding._plan(P.PATH_WY, 64)
+    assert P.library().elpa_hh_trafo_batched(pr, 1, None, C.byref(pl)) == -6
 
 
 def test_profile_api_without_calls():

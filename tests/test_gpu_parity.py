@@ -21,6 +21,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
 KS = [1, 2, 4, 6, 8, 16, 24, 32, 40, 48, 64]
 SPLIT_KS = [32, 48, 64, 80, 96]
+WY_KS = [32, 48, 64, 96]
 
 
 @pytest.fixture(scope="module")
@@ -91,6 +92,7 @@ def plans(nbw, dt):
     out = [(None, 0), (P.PATH_REF, 0)]
     out += [(P.PATH_STRIPE, k) for k in KS if P.plan_supported(nbw, code, P.PATH_STRIPE, k)]
     out += [(P.PATH_SPLIT, k) for k in SPLIT_KS if P.plan_supported(nbw, code, P.PATH_SPLIT, k)]
+    out += [(P.PATH_WY, k) for k in WY_KS if P.plan_supported(nbw, code, P.PATH_WY, k)]
     return out
 
 
@@ -199,6 +201,25 @@ def test_stripe_groups_on_streams(torch_dev):
         P.profile_enable(False)
 
 
+@pytest.mark.parametrize("dt,nbw,k", [("r64", 64, 64), ("r64", 64, 32), ("r64", 32, 96),
+                                       ("r32", 64, 64), ("r32", 32, 64)])
+def test_wy_path_tilings(torch_dev, dt, nbw, k):
+    """Compact-WY MFMA path: tiles of 1, 3 and 16 chase steps and two stripe
+    groups give bitwise equal results that match the oracle."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nev = 1000, 83
+    hh, tau, Z = oracle_inputs(n, nbw, nev, dt, 91 + k)
+    ref = bt.bt_tridiag_to_band(rounded(hh, dt), rounded(tau, dt), rounded(Z, dt), n, nbw)
+    outs = []
+    for steps, ns in ((1, 1), (3, 1), (16, 2)):
+        print(f"wy n={n} nbw={nbw} k={k} dt={dt} steps={steps} streams={ns}", flush=True)
+        got = run_gpu(torch, dev, hh, tau, Z, nbw, dt, P.PATH_WY, k, steps=steps, streams=ns)
+        assert checks.max_rel_err(got, ref) <= TOL[dt], steps
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 def test_profile_reports_main_kernel_sequence(torch_dev):
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
@@ -270,6 +291,8 @@ FULL = [
     (20000, 64, 2000, "r64", None), (20000, 64, 10000, "r64", None),
     (20000, 64, 20000, "r64", None),
     (20000, 64, 2000, "r64", (2, 32)),   # one-lane stripe kernel at full size
+    (20000, 64, 2000, "r64", (4, 64)),   # compact-WY MFMA path
+    (20000, 64, 2000, "r32", (4, 64)),
     (20000, 64, 2000, "r32", None), (20000, 64, 2000, "c64", None),
 ]
 
