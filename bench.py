@@ -47,10 +47,68 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--no-served", action="store_true", help="skip the served SCF stream leg")
+    ap.add_argument("--served-rates", default="120,250",
+                    help="Poisson arrival rates of the served stream (requests / s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark: copy a MIB-MiB device buffer 3 times "
                          "(reference kernel of known size for the HBM byte counters)")
     return ap.parse_args()
+
+
+def served_stream(args):
+    """The served SCF stream: 64 sequences x 20 solves, n_q ~ U{1000..6000},
+    nbw 64, nev = n, Poisson arrivals (rates below), each
+    request fp32 with probability 0.25.  Each sequence keeps its Q, reflectors
+    and tau (fp64 and fp32) resident; they are drawn on the device
+    (workload.device_*; the upstream stages that would produce them are not
+    timed).  The same trace is served with continuous batching and by the
+    plain one-call-at-a-time path, at each rate of args.served_rates (one
+    below the plain path's capacity, one above it)."""
+    import torch
+    import workload as W
+    from paper_1811_01277_amd.serve import Request, Server, latency_stats, run_plain
+    dev = torch.device("cuda:0")
+    nseq, steps = 64, 20
+    sizes = W.scf_sequence_sizes(nseq, 1000, 6000, seed=501)
+    rates = [float(x) for x in args.served_rates.split(",") if x]
+    g = torch.Generator(device=dev)
+    g.manual_seed(510000)
+    state = []
+    for q in range(nseq):
+        n = int(sizes[q])
+        hh, tau = W.device_reflectors(torch, n, 64, dev, g)
+        Z = W.device_block(torch, n, n, dev, g)           # column major
+        state.append({"r64": (Z, hh, tau), "r32": (Z.t().float().t(), hh.float(), tau.float())})
+    torch.cuda.synchronize()
+
+    def requests(rate):
+        t, sq, st, f32 = W.scf_trace(nseq, steps, rate=rate, p32=0.25)
+        out, last = [], {}
+        for i in range(len(t)):
+            q = int(sq[i])
+            Z, hh, tau = state[q]["r32" if f32[i] else "r64"]
+            out.append(Request(rid=i, q=Z, hh=hh, tau=tau, nbw=64, arrival=float(t[i]),
+                               after=last.get(q, -1), seq=q, step=int(st[i])))
+            last[q] = i
+        return out
+
+    warm = requests(1000.0)[:nseq]    # one solve per sequence, untimed
+    for r in warm:
+        r.arrival, r.after = 0.0, -1
+    Server(dev, slots=3, max_batch=32).run(warm)
+    runs = []
+    for rate in rates:
+        srv = Server(dev, slots=3, max_batch=32)
+        served = latency_stats(srv.run(requests(rate)))
+        plain = latency_stats(run_plain(requests(rate), dev))
+        runs.append({"rate_per_s": rate, "served": served, "plain": plain,
+                     "solves_per_s_vs_plain": round(served["solves_per_s"] /
+                                                    plain["solves_per_s"], 3),
+                     "batches": len(srv.batches)})
+    return {"workload": f"{nseq} sequences x {steps} solves, n ~ U{{1000..6000}}, nbw 64, "
+                        f"nev = n, Poisson arrivals, 25% fp32; slots 3, max batch 32",
+            "runs": runs}
 
 
 def recorded_traffic(workload):
@@ -216,8 +274,12 @@ def main():
                      "flops_per_launch": flops / launches,
                      "call_ms": [round(x, 3) for x in per]},
     }
+    del q, h, t
+    torch.cuda.empty_cache()
+    if not args.no_served:
+        out["served_stream"] = served_stream(args)
+        torch.cuda.empty_cache()
     if not args.no_cpu:
-        del q, h, t
         out["cpu_baseline"] = cpu_baseline(args, hh, tau, Z)
     print(json.dumps(out), flush=True)
 

@@ -74,7 +74,7 @@ enum {
                              (real fp64, nbw 32 or 64; the fp64 default) */
     ELPA_PATH_WY = 4      /* compact-WY aggregation of 16 reflectors at a time,
                              applied by MFMA tiles to an LDS-resident window (real fp64
-                             and fp32, nbw 32 or 64; single-problem calls only) */
+                             and fp32, nbw 32 or 64; the fp32 default) */
 };
 
 /* order of the tiles of one launch over the workgroup ids (elpa_hh_plan.order) */
@@ -165,6 +165,25 @@ typedef struct {
  */
 int elpa_hh_trafo_batched(const elpa_hh_problem *probs, int64_t count, void *stream,
                           const elpa_hh_plan *plan);
+
+/*
+ * Device workspace (bytes) that elpa_hh_trafo_plan allocates, in stream order,
+ * for one problem under `plan` (NULL = library choice): the stripe-major copy
+ * of Q and, for paths 3 and 4, the packed reflectors.  0 for no-ops and the
+ * reference path, -1 for invalid arguments or a plan that cannot run.  A
+ * batched call allocates the sum over its problems plus small descriptor
+ * tables.  For admission control by memory footprint (serving loops).
+ */
+int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dtype,
+                                const elpa_hh_plan *plan);
+
+/*
+ * Upper bound of the device workspace of elpa_hh_trafo_batched on the same
+ * arguments (the kernels a batched call picks, plus its descriptor and
+ * schedule tables); -1 for invalid arguments or a plan that cannot run.
+ */
+int64_t elpa_hh_workspace_bytes_batched(const elpa_hh_problem *probs, int64_t count,
+                                        const elpa_hh_plan *plan);
 
 /*
  * Whether an explicit plan can run (n, nbw, dtype): 1 yes, 0 no.

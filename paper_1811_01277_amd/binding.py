@@ -60,6 +60,11 @@ def library():
         L.elpa_hh_trafo_batched.restype = C.c_int
         L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
         L.elpa_hh_plan_supported.restype = C.c_int
+        L.elpa_hh_workspace_bytes.argtypes = [i64, i64, i64, i32, C.POINTER(_Plan)]
+        L.elpa_hh_workspace_bytes.restype = i64
+        L.elpa_hh_workspace_bytes_batched.argtypes = [C.POINTER(_Problem), i64,
+                                                      C.POINTER(_Plan)]
+        L.elpa_hh_workspace_bytes_batched.restype = i64
         L.elpa_hh_profile_enable.argtypes = [C.c_int]
         L.elpa_hh_profile_enable.restype = C.c_int
         L.elpa_hh_profile_last.argtypes = [C.POINTER(_Profile)]
@@ -117,6 +122,24 @@ def _plan(path, k, steps=0, order=0, streams=0):
 def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
     pl = _plan(path, k)
     return bool(library().elpa_hh_plan_supported(nbw, dtype, C.byref(pl) if pl else None))
+
+
+def workspace_bytes(n, nev, nbw, dtype, path=None, k=0):
+    """Device bytes one call allocates for this problem and plan (-1: invalid)."""
+    pl = _plan(path, k)
+    return int(library().elpa_hh_workspace_bytes(n, nev, nbw, dtype,
+                                                 C.byref(pl) if pl is not None else None))
+
+
+def workspace_bytes_batched(problems, path=None, k=0):
+    """Upper bound of the device bytes hh_trafo_batched allocates for a list
+    of (n, nev, nbw, dtype code) tuples (-1: invalid)."""
+    arr = (_Problem * max(1, len(problems)))()
+    for i, (n, nev, nbw, dt) in enumerate(problems):
+        arr[i] = _Problem(n, nev, nbw, max(n, 1), None, None, None, dt, 0)
+    pl = _plan(path, k)
+    return int(library().elpa_hh_workspace_bytes_batched(
+        arr, len(problems), C.byref(pl) if pl is not None else None))
 
 
 def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0, steps=0,

@@ -276,6 +276,37 @@ int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void* hh, const voi
   return elpa_hh_trafo_plan(n, nev, nbw, hh, tau, Q, ldq, dtype, stream, nullptr);
 }
 
+int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dtype,
+                                const elpa_hh_plan* plan) {
+  if (n < 0 || nev < 0 || nbw < 1 || elem_size(dtype) == 0) return -1;
+  int path = 0, rc = 0;
+  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc);
+  if (rc != ELPA_OK) return -1;
+  if (n <= 1 || nev == 0 || !se) return 0;
+  return (int64_t)se->workspace(n, nev);
+}
+
+int64_t elpa_hh_workspace_bytes_batched(const elpa_hh_problem* probs, int64_t count,
+                                        const elpa_hh_plan* plan) {
+  if (count < 0 || (count > 0 && !probs)) return -1;
+  int64_t total = 0, launches = 0, groups = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const elpa_hh_problem& p = probs[i];
+    if (p.n < 0 || p.nev < 0 || p.nbw < 1 || elem_size(p.dtype) == 0) return -1;
+    int path = 0, rc = 0;
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, plan, &path, &rc, true);
+    if (rc != ELPA_OK) return -1;
+    if (p.n <= 1 || p.nev == 0 || !se) continue;
+    total += (int64_t)se->workspace(p.n, p.nev);
+    ++groups;
+    // schedule entries: at most one per problem and launch (S >= 1)
+    launches += (p.n - 1 + se->k - 1) / se->k + (p.n - 1 + p.nbw - 1) / p.nbw;
+  }
+  if (groups == 0) return 0;
+  const int64_t desc = 256;  // generous bound of one descriptor / entry
+  return total + (groups + launches) * desc + 4096;
+}
+
 int elpa_hh_profile_enable(int on) {
   ehh::ProfState& p = ehh::prof_state();
   if (p.a) (void)hipEventDestroy(p.a);

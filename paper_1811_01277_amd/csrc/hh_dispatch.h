@@ -26,6 +26,8 @@ using StripeLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, in
                                     int num_cu);
 using BatchedLaunch = hipError_t (*)(const elpa_hh_problem* probs, const int64_t* idx,
                                      int64_t cnt, TileOpts opt, hipStream_t st, int num_cu);
+// Device workspace one problem's call allocates (bytes).
+using WorkspaceFn = size_t (*)(int64_t n, int64_t nev);
 using RefLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
                                  int64_t n, int64_t nev, int64_t nb, hipStream_t st);
 
@@ -37,6 +39,7 @@ struct StripeEntry {
   int occ;  // waves per SIMD the kernel is compiled for
   StripeLaunch fn;
   BatchedLaunch batched;  // null: no batched form
+  WorkspaceFn workspace;
 };
 
 const StripeEntry* stripe_table(int* size);  // one lane per column

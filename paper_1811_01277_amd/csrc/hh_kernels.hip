@@ -599,9 +599,14 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
   return err != hipSuccess ? err : e2;
 }
 
+template <typename E, int NB, int K>
+size_t diag_workspace(int64_t n, int64_t nev) {
+  return DiagPlan(n, nev, NB, K, 1).template qbytes<E>();
+}
+
 #define EHH_DIAG(E, DT, NB, K, OCC)                                                    \
   {ELPA_PATH_STRIPE, DT, NB, K, OCC, &launch_diag<E, NB, K, OCC>,                        \
-   &launch_diag_batched<E, NB, K, OCC>}
+   &launch_diag_batched<E, NB, K, OCC>, &diag_workspace<E, NB, K>}
 
 const StripeEntry* stripe_table(int* size) {
   static const StripeEntry table[] = {

@@ -510,9 +510,15 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
   return err != hipSuccess ? err : e2;
 }
 
+template <int NB, int K>
+size_t split_workspace(int64_t n, int64_t nev) {
+  const DiagPlan pl(n, nev, NB, K, 1, SplitGeom<NB, K>::SW);
+  return split_pbytes<NB, K>(pl.M, (n - 1 + NB - 1) / NB) + pl.template qbytes<double>();
+}
+
 #define EHH_SPLIT(NB, K, OCC, PD)                                               \
   {ELPA_PATH_SPLIT, 0, NB, K, OCC, &launch_split<NB, K, OCC, PD>,                 \
-   &launch_split_batched<NB, K, OCC, PD>}
+   &launch_split_batched<NB, K, OCC, PD>, &split_workspace<NB, K>}
 
 const StripeEntry* split_table(int* size) {
   static const StripeEntry table[] = {

@@ -71,18 +71,18 @@ struct WyGeom {
   static constexpr int SW = 16;            // columns per stripe (one wave)
 };
 
-// Pre-pass: build -U = -V T^T and V of sub-group u of (block m, step j).
+// Pre-pass: build -U = -V T^T and V of sub-group u of (block m, step j),
+// g = (m * Jmax + j) * SG + u; one 256-thread block.
 template <typename E, int NB, int K>
-__global__ __launch_bounds__(256) void k_wy_prep(const E* __restrict__ hh,
-                                                 const E* __restrict__ tau, int64_t n,
-                                                 int64_t Jmax, E* __restrict__ P) {
+__device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh,
+                                              const E* __restrict__ tau, int64_t n,
+                                              int64_t Jmax, E* __restrict__ P, int64_t g) {
   using Gm = WyGeom<NB, K>;
   constexpr int RP = Gm::RP;
   __shared__ double V[RP][17];
   __shared__ double Gr[16][17];
   __shared__ double T[16][17];
   __shared__ double tv[16];
-  const int64_t g = blockIdx.x;
   const int u = (int)(g % Gm::SG);
   const int64_t mj = g / Gm::SG;
   const int64_t m = mj / Jmax, j = mj % Jmax;
@@ -136,15 +136,29 @@ __global__ __launch_bounds__(256) void k_wy_prep(const E* __restrict__ hh,
   }
 }
 
+template <typename E, int NB, int K>
+__global__ __launch_bounds__(256) void k_wy_prep(const E* __restrict__ hh,
+                                                 const E* __restrict__ tau, int64_t n,
+                                                 int64_t Jmax, E* __restrict__ P) {
+  wy_prep_group<E, NB, K>(hh, tau, n, Jmax, P, blockIdx.x);
+}
+
+template <typename E, int NB, int K>
+__global__ __launch_bounds__(256) void k_wy_prep_b(const ProblemDesc* __restrict__ d, int count) {
+  const int b = (int)blockIdx.x;
+  const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::ptile0>(d, count, b)];
+  wy_prep_group<E, NB, K>((const E*)D.hh, (const E*)D.tau, D.n, D.Jmax, (E*)D.P, b - D.ptile0);
+}
+
 // Layout conversion between Q and 16-column stripes (element (r, 16c + l) at
-// Qs[(c*rows_pad + r)*16 + l]), 64 x 64 tiles through LDS, padding written as
-// zeros.
+// Qs[(c*rows_pad + r)*16 + l]), 64 x 64 tiles (row band rt, column band ct)
+// through LDS, padding written as zeros.
 template <typename E>
-__global__ __launch_bounds__(256) void k_to_rows16(const E* __restrict__ Q, int64_t ldq,
-                                                   int64_t n, int64_t nev, E* __restrict__ Qs,
-                                                   int64_t rows_pad, int64_t G) {
-  __shared__ E tile[64][65];
-  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+__device__ __forceinline__ void to_rows16_tile(const E* __restrict__ Q, int64_t ldq, int64_t n,
+                                               int64_t nev, E* __restrict__ Qs, int64_t rows_pad,
+                                               int64_t G, int64_t rt, int64_t ct,
+                                               E (*tile)[65]) {
+  const int64_t r0 = rt * 64, c0 = ct * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int cc = ty; cc < 64; cc += 4) {
     const int64_t r = r0 + tx, col = c0 + cc;
@@ -158,11 +172,11 @@ __global__ __launch_bounds__(256) void k_to_rows16(const E* __restrict__ Q, int6
 }
 
 template <typename E>
-__global__ __launch_bounds__(256) void k_from_rows16(const E* __restrict__ Qs, int64_t rows_pad,
-                                                     E* __restrict__ Q, int64_t ldq, int64_t n,
-                                                     int64_t nev, int64_t G) {
-  __shared__ E tile[64][65];
-  const int64_t r0 = (int64_t)blockIdx.x * 64, c0 = (int64_t)blockIdx.y * 64;
+__device__ __forceinline__ void from_rows16_tile(const E* __restrict__ Qs, int64_t rows_pad,
+                                                 E* __restrict__ Q, int64_t ldq, int64_t n,
+                                                 int64_t nev, int64_t G, int64_t rt, int64_t ct,
+                                                 E (*tile)[65]) {
+  const int64_t r0 = rt * 64, c0 = ct * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   {
     const int64_t col = c0 + tx, c = col / 16, l = col % 16;
@@ -176,6 +190,44 @@ __global__ __launch_bounds__(256) void k_from_rows16(const E* __restrict__ Qs, i
     const int64_t r = r0 + tx, col = c0 + cc;
     if (r < n && col < nev) Q[r + col * ldq] = tile[tx][cc];
   }
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_to_rows16(const E* __restrict__ Q, int64_t ldq,
+                                                   int64_t n, int64_t nev, E* __restrict__ Qs,
+                                                   int64_t rows_pad, int64_t G) {
+  __shared__ E tile[64][65];
+  to_rows16_tile<E>(Q, ldq, n, nev, Qs, rows_pad, G, blockIdx.x, blockIdx.y, tile);
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_from_rows16(const E* __restrict__ Qs, int64_t rows_pad,
+                                                     E* __restrict__ Q, int64_t ldq, int64_t n,
+                                                     int64_t nev, int64_t G) {
+  __shared__ E tile[64][65];
+  from_rows16_tile<E>(Qs, rows_pad, Q, ldq, n, nev, G, blockIdx.x, blockIdx.y, tile);
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_to_rows16_b(const ProblemDesc* __restrict__ d,
+                                                     int count) {
+  __shared__ E tile[64][65];
+  const int t = (int)blockIdx.x;
+  const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::tile0>(d, count, t)];
+  const int local = t - D.tile0;
+  to_rows16_tile<E>((const E*)D.Q, D.ldq, D.n, D.nev, (E*)D.Qs, D.rows_pad, D.G, local / D.GT,
+                    local % D.GT, tile);
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_from_rows16_b(const ProblemDesc* __restrict__ d,
+                                                       int count) {
+  __shared__ E tile[64][65];
+  const int t = (int)blockIdx.x;
+  const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::otile0>(d, count, t)];
+  const int local = t - D.otile0;
+  from_rows16_tile<E>((const E*)D.Qs, D.rows_pad, (E*)D.Q, D.ldq, D.n, D.nev, D.G,
+                      local / D.GT, local % D.GT, tile);
 }
 
 // The stripe's window in LDS: rows 0 .. W-1 (window row i = stripe row
@@ -352,6 +404,21 @@ __global__ __launch_bounds__(64, OCC) void k_wy(const E* __restrict__ P, int64_t
   run_wy_tile<E, NB, K>(P, Jmax, Qs, rows_pad, n, c, m, t - (M - 1 - m), S, win, wbuf);
 }
 
+template <typename E, int NB, int K, int OCC>
+__global__ __launch_bounds__(64, OCC) void k_wy_b(const ProblemDesc* __restrict__ d,
+                                                  const DiagEntry* __restrict__ e, int ecount,
+                                                  int t, int xcd) {
+  __shared__ E win[(NB + K) * 16];
+  __shared__ E wbuf[256];
+  const int b = tile_of((int)blockIdx.x, (int)gridDim.x, xcd);
+  const DiagEntry& E0 = e[find_by<DiagEntry, &DiagEntry::tile0>(e, ecount, b)];
+  const ProblemDesc& D = d[E0.p];
+  const int local = b - E0.tile0;
+  const int m = E0.m0 + local / D.G;
+  run_wy_tile<E, NB, K>((const E*)D.P, D.Jmax, (E*)D.Qs, D.rows_pad, D.n, local % D.G, m,
+                        t - (D.M - 1 - m), D.S, win, wbuf);
+}
+
 template <typename E, int NB, int K>
 size_t wy_pbytes(int64_t M, int64_t Jmax) {
   using Gm = WyGeom<NB, K>;
@@ -414,8 +481,128 @@ hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int6
   return err != hipSuccess ? err : e2;
 }
 
+// Batched: problems idx[0..cnt) of probs (element type E, semi-bandwidth NB,
+// validated by the caller); all problems' diagonal schedules side by side.
+template <typename E, int NB, int K, int OCC>
+hipError_t launch_wy_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
+                             TileOpts opt, hipStream_t st, int num_cu) {
+  using Gm = WyGeom<NB, K>;
+  const int64_t S = opt.steps;
+  static const int64_t slots = wave_slots(k_wy_b<E, NB, K, OCC>, num_cu);
+  std::vector<ProblemDesc> d;
+  std::vector<DiagPlan> plans;
+  int64_t total_cols = 0;
+  for (int64_t i = 0; i < cnt; ++i) {
+    const elpa_hh_problem& p = probs[idx[i]];
+    if (p.n > 1 && p.nev > 0) total_cols += p.nev;
+  }
+  for (int64_t i = 0; i < cnt; ++i) {
+    const elpa_hh_problem& p = probs[idx[i]];
+    if (p.n <= 1 || p.nev == 0) continue;
+    const int64_t s = S > 0 ? S : choose_steps(p.n, total_cols, NB, K, slots, Gm::SW);
+    plans.emplace_back(p.n, p.nev, NB, K, s, Gm::SW);
+    ProblemDesc x{};
+    x.hh = p.hh;
+    x.tau = p.tau;
+    x.Q = p.Q;
+    x.n = p.n;
+    x.nev = p.nev;
+    x.ldq = p.ldq;
+    d.push_back(x);
+  }
+  if (d.empty()) return hipSuccess;
+  size_t off = 0, tiles = 0, otiles = 0, ptiles = 0;
+  int64_t T = 0;
+  std::vector<size_t> pat(d.size()), qat(d.size());
+  for (size_t i = 0; i < d.size(); ++i) {
+    const DiagPlan& pl = plans[i];
+    const int64_t Jmax = (pl.n - 1 + NB - 1) / NB;
+    d[i].G = (int)pl.G;
+    d[i].GT = (int)((pl.nev + 63) / 64);
+    d[i].M = (int)pl.M;
+    d[i].S = (int)pl.S;
+    d[i].rows_pad = pl.rows_pad;
+    d[i].Jmax = Jmax;
+    d[i].tile0 = (int)tiles;
+    d[i].otile0 = (int)otiles;
+    d[i].ptile0 = (int)ptiles;
+    tiles += (size_t)(pl.rows_pad / 64 * d[i].GT);
+    otiles += (size_t)((pl.n + 63) / 64 * d[i].GT);
+    ptiles += (size_t)(pl.M * Jmax * Gm::SG);
+    pat[i] = off;
+    off += wy_pbytes<E, NB, K>(pl.M, Jmax);
+    qat[i] = off;
+    off += pl.template qbytes<E>();
+    T = std::max(T, pl.T);
+  }
+  std::vector<DiagEntry> ent;
+  std::vector<int64_t> eoff((size_t)T + 1, 0), etiles((size_t)T, 0);
+  for (int64_t t = 0; t < T; ++t) {
+    eoff[(size_t)t] = (int64_t)ent.size();
+    int64_t tl = 0;
+    for (size_t i = 0; i < d.size(); ++i) {
+      int64_t m0, c;
+      plans[i].active(t, &m0, &c);
+      if (c == 0) continue;
+      ent.push_back(DiagEntry{(int)i, (int)m0, (int)c, (int)tl});
+      tl += c * plans[i].G;
+    }
+    etiles[(size_t)t] = tl;
+  }
+  eoff[(size_t)T] = (int64_t)ent.size();
+  if (tiles >= (size_t)INT32_MAX || otiles >= (size_t)INT32_MAX || ptiles >= (size_t)INT32_MAX)
+    return hipErrorInvalidValue;
+  for (int64_t x : etiles)
+    if (x >= INT32_MAX) return hipErrorInvalidValue;
+  const size_t dbytes = align256(d.size() * sizeof(ProblemDesc));
+  const size_t ebytes = align256(std::max<size_t>(1, ent.size()) * sizeof(DiagEntry));
+  char* ws = nullptr;
+  hipError_t err = hipMallocAsync((void**)&ws, dbytes + ebytes + off, st);
+  if (err != hipSuccess) return err;
+  for (size_t i = 0; i < d.size(); ++i) {
+    d[i].P = ws + dbytes + ebytes + pat[i];
+    d[i].Qs = ws + dbytes + ebytes + qat[i];
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  PinnedStaging& stage = PinnedStaging::for_device(dev);
+  err = stage.upload(ws, d.data(), d.size() * sizeof(ProblemDesc), st);
+  if (err == hipSuccess && !ent.empty())
+    err = stage.upload(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry), st);
+  if (err != hipSuccess) {
+    (void)hipFreeAsync(ws, st);
+    return err;
+  }
+  const ProblemDesc* dd = (const ProblemDesc*)ws;
+  const DiagEntry* de = (const DiagEntry*)(ws + dbytes);
+  const int count = (int)d.size();
+  hipLaunchKernelGGL((k_wy_prep_b<E, NB, K>), dim3((unsigned)ptiles), dim3(256), 0, st, dd, count);
+  hipLaunchKernelGGL(k_to_rows16_b<E>, dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
+  ProfScope prof(st, K, S);
+  for (int64_t t = 0; t < T; ++t) {
+    const int64_t ne = eoff[(size_t)t + 1] - eoff[(size_t)t];
+    if (ne == 0) continue;
+    prof.before(st);
+    hipLaunchKernelGGL((k_wy_b<E, NB, K, OCC>), dim3((unsigned)etiles[(size_t)t]), dim3(64), 0, st,
+                       dd, de + eoff[(size_t)t], (int)ne, (int)t, opt.xcd);
+    prof.after(st);
+  }
+  prof.end();
+  hipLaunchKernelGGL(k_from_rows16_b<E>, dim3((unsigned)otiles), dim3(256), 0, st, dd, count);
+  err = hipGetLastError();
+  const hipError_t e2 = hipFreeAsync(ws, st);
+  return err != hipSuccess ? err : e2;
+}
+
+template <typename E, int NB, int K>
+size_t wy_workspace(int64_t n, int64_t nev) {
+  const DiagPlan pl(n, nev, NB, K, 1, WyGeom<NB, K>::SW);
+  return wy_pbytes<E, NB, K>(pl.M, (n - 1 + NB - 1) / NB) + pl.template qbytes<E>();
+}
+
 #define EHH_WY(E, DT, NB, K, OCC) \
-  {ELPA_PATH_WY, DT, NB, K, OCC, &launch_wy<E, NB, K, OCC>, nullptr}
+  {ELPA_PATH_WY,     DT, NB, K, OCC, &launch_wy<E, NB, K, OCC>, &launch_wy_batched<E, NB, K, OCC>, \
+   &wy_workspace<E, NB, K>}
 
 const StripeEntry* wy_table(int* size) {
   static const StripeEntry table[] = {

@@ -1,0 +1,207 @@
+"""Served stream of back-transformation requests on one GPU (continuous
+batching).
+
+A request is one tridiagonal->band back-transformation Q <- H ... H Q of a
+problem whose Q, reflectors and tau are resident on the device.  An SCF cycle
+solves a series of eigenproblems of one size whose matrix changes only
+slightly from step to step, in single or double precision (Kus et al.,
+Sec. 5): a sequence keeps its buffers across its consecutive solves, and the
+upstream stages that refill them are not part of the timed service.
+
+Scheduling (all of it host logic around the C ABI; every step of the
+computation runs in the HIP library):
+
+* admission by device-memory footprint: a request is launched only while
+  the library's workspace for the in-flight work
+  (elpa_hh_workspace_bytes_batched) stays within the budget;
+* continuous batching: `slots` streams; whenever a slot is free, every ready
+  request that fits the budget (up to max_batch, oldest first) is launched
+  on it as one elpa_hh_trafo_batched call, so requests that arrive while
+  others run are admitted as soon as a slot and memory free up and their work
+  overlaps on the device;
+* a lone request on an otherwise idle device runs as a single call with the
+  library's stripe-group streams (the batched call keeps to its slot's
+  stream, so concurrent slots never share the library's streams);
+* completion is tracked with events; a solve that depends on an earlier one
+  (the next step of the same SCF sequence) becomes ready when that completes.
+
+Latency of a request = completion - max(arrival, completion of the solve it
+depends on).  `run_plain` serves the same requests one call at a time on one
+stream, as the baseline.
+"""
+import time
+from dataclasses import dataclass
+
+from . import binding as B
+
+__all__ = ["Request", "Server", "run_plain", "latency_stats"]
+
+
+@dataclass
+class Request:
+    rid: int
+    q: object            # column-major (n, nev) device tensor, overwritten
+    hh: object           # reflectors (same dtype as q)
+    tau: object
+    nbw: int
+    arrival: float       # seconds after the trace start
+    after: int = -1      # rid that must complete first (-1: none)
+    seq: int = -1
+    step: int = -1
+    t_ready: float = None
+    t_start: float = None
+    t_done: float = None
+
+    def flops(self):
+        n, nev = self.q.shape
+        return (8 if self.q.is_complex() else 2) * n * (n - 1) * nev
+
+
+def _dtype_code(q):
+    return B._dtype_code(q)
+
+
+def footprint(r):
+    """Library workspace bytes of one request in a batched call (the sum over a
+    batch bounds the batch's workspace)."""
+    if getattr(r, "_fp", None) is None:
+        n, nev = r.q.shape
+        r._fp = max(0, B.workspace_bytes_batched([(n, nev, r.nbw, _dtype_code(r.q))]))
+    return r._fp
+
+
+class Server:
+    def __init__(self, device, slots=3, budget_bytes=None, max_batch=32, poll_s=50e-6):
+        import torch
+        self.torch = torch
+        self.device = device
+        self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        if budget_bytes is None:
+            free, _ = torch.cuda.mem_get_info(device)
+            budget_bytes = int(0.5 * free)
+        self.budget = int(budget_bytes)
+        self.max_batch = max_batch
+        self.poll_s = poll_s
+        self.batches = []       # (slot, size, bytes) of every launch
+        self.max_in_use = 0     # peak admitted workspace bytes
+        self.max_busy = 0       # peak number of slots running at once
+
+    def run(self, requests):
+        """Replay the requests' arrival times against the wall clock; returns
+        when all are done.  Requests are updated in place with their times."""
+        torch = self.torch
+        pending = sorted(requests, key=lambda r: r.arrival)
+        done_at = {}
+        waiting, ready = [], []
+        busy = [None] * len(self.streams)  # (event, batch, bytes, forked)
+        in_use = 0
+        left = len(pending)
+        pi = 0
+        torch.cuda.synchronize(self.device)
+        t0 = time.perf_counter()
+        while left:
+            now = time.perf_counter() - t0
+            progress = False
+            for i, b in enumerate(busy):
+                if b is not None and b[0].query():
+                    for r in b[1]:
+                        r.t_done = now
+                        done_at[r.rid] = now
+                    in_use -= b[2]
+                    left -= len(b[1])
+                    busy[i] = None
+                    progress = True
+            while pi < len(pending) and pending[pi].arrival <= now:
+                waiting.append(pending[pi])
+                pi += 1
+            still = []
+            for r in waiting:
+                if r.after < 0 or r.after in done_at:
+                    r.t_ready = max(r.arrival, done_at.get(r.after, 0.0))
+                    ready.append(r)
+                else:
+                    still.append(r)
+            waiting = still
+            for i, b in enumerate(busy):
+                if b is not None or not ready:
+                    continue
+                batch, nbytes, rest = [], 0, []
+                for r in ready:
+                    f = footprint(r)
+                    fits = in_use + nbytes + f <= self.budget
+                    # an idle device always takes the oldest request
+                    if len(batch) < self.max_batch and (fits or (in_use == 0 and not batch)):
+                        batch.append(r)
+                        nbytes += f
+                    else:
+                        rest.append(r)
+                if not batch:
+                    break
+                ready = rest
+                st = self.streams[i]
+                idle = all(x is None for x in busy)
+                if len(batch) == 1 and idle:
+                    r = batch[0]
+                    B.hh_trafo(r.q, r.hh, r.tau, r.nbw, stream=st)  # library plan
+                else:
+                    B.hh_trafo_batched([(r.q, r.hh, r.tau, r.nbw) for r in batch], stream=st,
+                                       streams=1)
+                ev = torch.cuda.Event()
+                ev.record(st)
+                for r in batch:
+                    r.t_start = now
+                busy[i] = (ev, batch, nbytes)
+                in_use += nbytes
+                self.batches.append((i, len(batch), nbytes))
+                self.max_in_use = max(self.max_in_use, in_use)
+                self.max_busy = max(self.max_busy, sum(x is not None for x in busy))
+                progress = True
+            if not progress:
+                time.sleep(self.poll_s)
+        return requests
+
+
+def run_plain(requests, device, poll_s=50e-6):
+    """Baseline: one elpa_hh_trafo call at a time on one stream, in the order
+    requests become ready, each waited for before the next starts."""
+    import torch
+    st = torch.cuda.Stream(device=device)
+    order = sorted(requests, key=lambda r: r.arrival)
+    done_at = {}
+    torch.cuda.synchronize(device)
+    t0 = time.perf_counter()
+    queue = list(order)
+    while queue:
+        now = time.perf_counter() - t0
+        # oldest request whose dependency is met (requests are served in order)
+        r = None
+        for cand in queue:
+            if cand.after < 0 or cand.after in done_at:
+                r = cand
+                break
+        if r is None or r.arrival > now:
+            time.sleep(poll_s)
+            continue
+        queue.remove(r)
+        r.t_ready = max(r.arrival, done_at.get(r.after, 0.0))
+        r.t_start = now
+        B.hh_trafo(r.q, r.hh, r.tau, r.nbw, stream=st)
+        st.synchronize()
+        r.t_done = time.perf_counter() - t0
+        done_at[r.rid] = r.t_done
+    return requests
+
+
+def latency_stats(requests):
+    """solves/s over the trace (first arrival to last completion), counted
+    flops per second, p50 / p99 / max latency in ms."""
+    import numpy as np
+    lat = np.array([r.t_done - r.t_ready for r in requests]) * 1e3
+    span = max(r.t_done for r in requests) - min(r.arrival for r in requests)
+    fl = sum(r.flops() for r in requests)
+    return {"solves": len(requests), "span_s": round(span, 4),
+            "solves_per_s": round(len(requests) / span, 2),
+            "gflops": round(fl / span / 1e9, 1),
+            "p50_ms": round(float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "max_ms": round(float(lat.max()), 3)}

@@ -132,12 +132,32 @@ def test_plan_support_table():
     assert P.library().elpa_hh_trafo_plan(10, 5, 2, 8, 8, 8, 10, P.R64, None, C.byref(pl)) == -6
 
 
-def test_batched_rejects_family_without_batched_form():
-    # the WY path has no batched launcher: the whole call is refused up front
-    pr = (P.binding._Problem * 1)()
-    pr[0] = P.binding._Problem(100, 10, 64, 100, 8, 8, 8, P.R64, 0)
-    pl = P.binding._plan(P.PATH_WY, 64)
-    assert P.library().elpa_hh_trafo_batched(pr, 1, None, C.byref(pl)) == -6
+def test_workspace_bytes():
+    # reference path and no-ops allocate nothing; invalid arguments give -1
+    assert P.workspace_bytes(100, 10, 7, P.R64) == 0
+    assert P.workspace_bytes(1, 10, 64, P.R64) == 0
+    assert P.workspace_bytes(100, 10, 0, P.R64) == -1
+    assert P.workspace_bytes(100, 10, 64, 9) == -1
+    assert P.workspace_bytes(100, 10, 64, P.R64, P.PATH_SPLIT, 63) == -1
+    # split path at n = nev = 20000, k = 80: stripe copy (rows_pad x 625 x 32 fp64)
+    # plus packed reflectors (M x Jmax x k records of 68 values, +32 values)
+    n, nev, nbw, k = 20000, 20000, 64, 80
+    rows_pad = -(-(n + nbw + k) // 64) * 64
+    M, Jmax = -(-(n - 1) // k), -(-(n - 1) // nbw)
+    al = lambda x: -(-x // 256) * 256
+    want = al((M * Jmax * k * 68 + 32) * 8) + al(rows_pad * (-(-nev // 32)) * 32 * 8)
+    assert P.workspace_bytes(n, nev, nbw, P.R64, P.PATH_SPLIT, k) == want
+    assert P.workspace_bytes(n, nev, nbw, P.R64) == want        # the library default
+    assert P.workspace_bytes(n, nev, nbw, P.C64) > 0
+    # batched: the kernels a batched call picks, plus descriptor tables
+    one = P.workspace_bytes_batched([(n, nev, nbw, P.R64)])
+    assert one >= want and one < want + (1 << 20)
+    two = P.workspace_bytes_batched([(n, nev, nbw, P.R64), (500, 300, 32, P.R32)])
+    assert two > one
+    assert P.workspace_bytes_batched([(500, 300, 32, P.R32)]) >= \
+        P.workspace_bytes(500, 300, 32, P.R32, P.PATH_WY)
+    assert P.workspace_bytes_batched([(500, 300, 0, P.R32)]) == -1
+    assert P.workspace_bytes_batched([]) == 0
 
 
 def test_profile_api_without_calls():

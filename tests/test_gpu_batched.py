@@ -74,6 +74,37 @@ def test_batch_matches_oracle_and_single_calls(torch_dev):
         assert torch.equal(q, s), "batched result differs from the single call"
 
 
+def test_fp32_batch_on_wy_path_equals_single_calls(torch_dev):
+    """fp32 problems (library choice: the compact-WY MFMA path) give bitwise the
+    same result in a batch as alone, and match the oracle."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    sizes = [(300, 64, 150), (517, 64, 517), (130, 32, 33), (260, 64, 97)]
+    probs, host = [], []
+    for i, (n, nbw, nev) in enumerate(sizes):
+        p, h = make(torch, dev, n, nbw, nev, "r32", 4000 + i)
+        probs.append(p)
+        host.append(h)
+    singles = []
+    for (q, h, t, nbw) in probs:
+        qq = q.clone()
+        P.hh_trafo(qq, h, t, nbw)
+        singles.append(qq)
+    P.profile_enable(True)
+    try:
+        P.hh_trafo_batched(probs)
+        pr = P.profile_last()
+    finally:
+        P.profile_enable(False)
+    torch.cuda.synchronize()
+    assert pr["path"] == P.PATH_AUTO or pr["launches"] > 0
+    for (q, _, _, nbw), (hh, tau, Z), s, (n, _, nev) in zip(probs, host, singles, sizes):
+        assert torch.equal(q, s), "batched fp32 result differs from the single call"
+        ref = bt.bt_tridiag_to_band(rounded(hh, "r32"), rounded(tau, "r32"), rounded(Z, "r32"),
+                                    n, nbw)
+        assert checks.max_rel_err(q.cpu().numpy().astype(np.float64), ref) <= TOL["r32"]
+
+
 def test_batch_mixed_dtypes(torch_dev):
     torch, dev = torch_dev
     import paper_1811_01277_amd as P

@@ -13,6 +13,12 @@ reflector_layout(n, b)       sweep, chase step, row start and length per slot
 synthetic_reflectors(...)    random unit-norm-preserving Householder reflectors
                              laid out as the band->tridiagonal chase emits them
 gaussian_block(n, nev, ...)  a dense n x nev block standing in for eigenvectors
+device_reflectors, device_block   the same drawn on the GPU with torch (served
+                             stream throughput runs)
+
+Workload sizes and traces
+-------------------------
+batched_sizes, scf_sequence_sizes, scf_trace (Poisson arrivals, fp32 share)
 
 The synthetic reflectors have the structure of the real ones: v[0] = 1, the
 other L-1 entries of size about 1/sqrt(b), zero padding past L, and a tau that
@@ -26,7 +32,8 @@ import numpy as np
 __all__ = [
     "sym_gaussian", "herm_gaussian", "haar_spectrum", "reflector_layout",
     "synthetic_reflectors", "gaussian_block", "to_dtype",
-    "batched_sizes", "scf_sequence_sizes",
+    "batched_sizes", "scf_sequence_sizes", "scf_trace",
+    "device_reflectors", "device_block",
 ]
 
 
@@ -133,3 +140,46 @@ def batched_sizes(count=256, lo=200, hi=2000, seed=401):
 def scf_sequence_sizes(count=64, lo=1000, hi=6000, seed=501):
     """Per-sequence sizes of the served SCF stream: n_q ~ U{lo..hi}."""
     return _rng(seed).integers(lo, hi + 1, size=count)
+
+
+def scf_trace(nseq=64, steps=20, rate=200.0, p32=0.25, seed_arrivals=502, seed_dtypes=503):
+    """Arrival trace of the served SCF stream: nseq sequences of `steps` solves.
+
+    A Poisson process of the given rate (requests per second) gives
+    nseq*steps arrival times; request i belongs to sequence i % nseq as its
+    step i // nseq (each sequence's solves arrive in order, and a solve is
+    also held back until the sequence's previous solve has completed).  Each
+    request is fp32 with probability p32, else fp64.  Returns
+    (arrival seconds, sequence, step, is_fp32) arrays.
+    """
+    total = nseq * steps
+    t = np.cumsum(_rng(seed_arrivals).exponential(1.0 / rate, size=total))
+    i = np.arange(total)
+    fp32 = _rng(seed_dtypes).random(total) < p32
+    return t - t[0], i % nseq, i // nseq, fp32
+
+
+def device_reflectors(torch, n, b, device, generator, dtype=None):
+    """synthetic_reflectors drawn on the device with a torch generator (same
+    structure and distribution, another random stream): for throughput runs
+    whose inputs stand in for an upstream stage that produces them on the
+    GPU.  Returns (hh, tau) 1-D device tensors (fp64 unless dtype)."""
+    _, _, _, LL = reflector_layout(n, b)
+    N = LL.size
+    dt = dtype or torch.float64
+    L = torch.from_numpy(LL).to(device)
+    hh = torch.randn((N, b), generator=generator, device=device, dtype=torch.float64)
+    hh *= 1.0 / np.sqrt(b)
+    hh[:, 0] = 1.0
+    hh.masked_fill_(torch.arange(b, device=device)[None, :] >= L[:, None], 0.0)
+    tau = 2.0 / (hh * hh).sum(dim=1)
+    tau.masked_fill_(L == 1, 0.0)
+    return hh.reshape(-1).to(dt), tau.to(dt)
+
+
+def device_block(torch, n, nev, device, generator, dtype=None):
+    """gaussian_block drawn on the device: column-major (n, nev) tensor with
+    N(0, 1/n) entries (fp64 unless dtype)."""
+    z = torch.randn((nev, n), generator=generator, device=device, dtype=torch.float64)
+    z *= 1.0 / np.sqrt(n)
+    return z.to(dtype or torch.float64).t()
