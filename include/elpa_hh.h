@@ -216,6 +216,41 @@ typedef struct {
 int elpa_hh_profile_enable(int on);
 int elpa_hh_profile_last(elpa_hh_profile *out);
 
+/*
+ * Plan tuner.  The library keeps a per-process cache of plans keyed by
+ * (dtype, nbw, size class of n, size class of nev); size classes are quarter
+ * octaves (floor(4 log2 x)), so sizes within about 19 % share a plan.  Calls
+ * without an explicit plan (NULL, or a plan whose fields are all 0) use the
+ * cached plan of their class when there is one; batched calls do so per
+ * problem (problems whose plans pick different kernels run as separate launch
+ * sequences, in order).
+ *
+ * elpa_hh_tune times candidate plans on a scratch copy of Q (Q itself is not
+ * modified; the call allocates ldq*nev elements and waits for `stream`) and
+ * caches and returns the fastest.  level 0: each kernel family's default k;
+ * 1: every compiled k; 2: also explicit chase steps per tile; every candidate
+ * with 1 and 2 stripe-group streams.  Same arguments and errors as
+ * elpa_hh_trafo (n <= 1 or nev == 0: ELPA_ERR_ARG, nothing to tune).
+ *
+ * elpa_hh_tuner_set stores an explicit plan for a class (ELPA_ERR_PLAN if it
+ * cannot run), elpa_hh_tuner_get reads it (1 found, 0 not), _size counts the
+ * entries, _clear empties the cache.  elpa_hh_tuner_save / _load write and
+ * read a text file ("elpa_hh_tuner 1", then one line per entry: dtype nbw
+ * n_class nev_class path k steps order streams); a file that does not parse
+ * or names a plan that cannot run is refused as a whole (ELPA_ERR_ARG) and
+ * the cache is left as it was; loaded entries replace entries of the same key.
+ */
+int elpa_hh_tune(int64_t n, int64_t nev, int64_t nbw, const void *hh, const void *tau,
+                 const void *Q, int64_t ldq, int32_t dtype, void *stream, int32_t level,
+                 elpa_hh_plan *best);
+int elpa_hh_tuner_set(int32_t dtype, int64_t nbw, int64_t n, int64_t nev,
+                      const elpa_hh_plan *plan);
+int elpa_hh_tuner_get(int32_t dtype, int64_t nbw, int64_t n, int64_t nev, elpa_hh_plan *out);
+int64_t elpa_hh_tuner_size(void);
+void elpa_hh_tuner_clear(void);
+int elpa_hh_tuner_save(const char *path);
+int elpa_hh_tuner_load(const char *path);
+
 /* Static message for a return code (never NULL). */
 const char *elpa_strerror(int code);
 

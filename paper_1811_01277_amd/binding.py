@@ -65,6 +65,20 @@ def library():
         L.elpa_hh_workspace_bytes_batched.argtypes = [C.POINTER(_Problem), i64,
                                                       C.POINTER(_Plan)]
         L.elpa_hh_workspace_bytes_batched.restype = i64
+        L.elpa_hh_tune.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, i32, C.POINTER(_Plan)]
+        L.elpa_hh_tune.restype = C.c_int
+        L.elpa_hh_tuner_set.argtypes = [i32, i64, i64, i64, C.POINTER(_Plan)]
+        L.elpa_hh_tuner_set.restype = C.c_int
+        L.elpa_hh_tuner_get.argtypes = [i32, i64, i64, i64, C.POINTER(_Plan)]
+        L.elpa_hh_tuner_get.restype = C.c_int
+        L.elpa_hh_tuner_size.argtypes = []
+        L.elpa_hh_tuner_size.restype = i64
+        L.elpa_hh_tuner_clear.argtypes = []
+        L.elpa_hh_tuner_clear.restype = None
+        L.elpa_hh_tuner_save.argtypes = [C.c_char_p]
+        L.elpa_hh_tuner_save.restype = C.c_int
+        L.elpa_hh_tuner_load.argtypes = [C.c_char_p]
+        L.elpa_hh_tuner_load.restype = C.c_int
         L.elpa_hh_profile_enable.argtypes = [C.c_int]
         L.elpa_hh_profile_enable.restype = C.c_int
         L.elpa_hh_profile_last.argtypes = [C.POINTER(_Profile)]
@@ -94,6 +108,62 @@ def profile_last():
     return {"kernel_ms": out.kernel_ms, "launches": out.launches, "path": out.path,
             "k": out.k, "steps": out.steps, "sum_launch_ms": out.sum_launch_ms,
             "streams": out.streams}
+
+
+def _plan_dict(p):
+    return {"path": p.path, "k": p.k, "steps": p.steps, "order": p.order, "streams": p.streams}
+
+
+def _check(rc):
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+
+
+def tune(q, hh, tau, nbw, level=0, stream=None):
+    """Time candidate plans for this problem (Q is not modified), cache the
+    fastest for its size class and return it as a dict."""
+    import torch
+    n, nev = q.shape
+    ldq = q.stride(1) if nev > 1 else max(n, 1)
+    if stream is None:
+        st = torch.cuda.current_stream(q.device).cuda_stream
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = stream.cuda_stream
+    out = _Plan()
+    _check(library().elpa_hh_tune(n, nev, nbw, C.c_void_p(hh.data_ptr()),
+                                  C.c_void_p(tau.data_ptr()), C.c_void_p(q.data_ptr()), ldq,
+                                  _dtype_code(q), C.c_void_p(st), level, C.byref(out)))
+    return _plan_dict(out)
+
+
+def tuner_set(dtype, nbw, n, nev, path=0, k=0, steps=0, order=0, streams=0):
+    pl = _Plan(path, k, steps, order, streams, 0)
+    _check(library().elpa_hh_tuner_set(dtype, nbw, n, nev, C.byref(pl)))
+
+
+def tuner_get(dtype, nbw, n, nev):
+    """The cached plan of the size class of (n, nev) as a dict, or None."""
+    out = _Plan()
+    found = library().elpa_hh_tuner_get(dtype, nbw, n, nev, C.byref(out))
+    return _plan_dict(out) if found == 1 else None
+
+
+def tuner_size():
+    return int(library().elpa_hh_tuner_size())
+
+
+def tuner_clear():
+    library().elpa_hh_tuner_clear()
+
+
+def tuner_save(path):
+    _check(library().elpa_hh_tuner_save(os.fsencode(path)))
+
+
+def tuner_load(path):
+    _check(library().elpa_hh_tuner_load(os.fsencode(path)))
 
 
 def strerror(code):

@@ -128,6 +128,16 @@ int device_cus() {
   return cache[dev];
 }
 
+// The plan a call runs: the caller's explicit plan, else the tuner's plan for
+// the size class of (n, nev) if there is one, else NULL (library choice).
+const elpa_hh_plan* effective_plan(int32_t dtype, int64_t nbw, int64_t n, int64_t nev,
+                                   const elpa_hh_plan* plan, elpa_hh_plan* buf) {
+  const bool automatic = !plan || (plan->path == ELPA_PATH_AUTO && plan->k == 0 &&
+                                   plan->steps == 0 && plan->order == 0 && plan->streams == 0);
+  if (automatic && ehh::tuner_lookup(dtype, nbw, n, nev, buf)) return buf;
+  return plan;
+}
+
 // Tile options of a plan (NULL = library choice).
 ehh::TileOpts tile_opts(const elpa_hh_plan* plan) {
   ehh::TileOpts o{};
@@ -202,6 +212,8 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
                        const elpa_hh_plan* plan) {
   int rc = validate(n, nev, nbw, hh, tau, Q, ldq, dtype);
   if (rc != ELPA_OK) return rc;
+  elpa_hh_plan tuned{};
+  plan = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0;
   const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc);
   if (rc != ELPA_OK) return rc;
@@ -231,20 +243,24 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
   }
   // group by (dtype, nbw): one launch sequence per group with a stripe kernel,
   // the reference kernel one problem at a time otherwise
-  std::map<std::pair<int32_t, int64_t>, std::vector<int64_t>> groups;
-  std::map<std::pair<int32_t, int64_t>, const ehh::StripeEntry*> entry;
+  // problems that run the same kernel (a tuned plan may pick another k for
+  // another size class) share one launch sequence, in order of first use
+  std::vector<const ehh::StripeEntry*> order;
+  std::map<const ehh::StripeEntry*, std::vector<int64_t>> groups;
   std::vector<int64_t> singles;
   int last_path = ELPA_PATH_REF;
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
+    elpa_hh_plan tuned{};
+    const elpa_hh_plan* pp = effective_plan(p.dtype, p.nbw, p.n, p.nev, plan, &tuned);
     int path = 0, rc = 0;
-    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, plan, &path, &rc, true);
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, pp, &path, &rc, true);
     if (rc != ELPA_OK) return rc;
     if (p.n <= 1 || p.nev == 0) continue;
     last_path = path;
     if (se) {
-      groups[{p.dtype, p.nbw}].push_back(i);
-      entry[{p.dtype, p.nbw}] = se;
+      if (!groups.count(se)) order.push_back(se);
+      groups[se].push_back(i);
     } else {
       singles.push_back(i);
     }
@@ -253,9 +269,9 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   prof_begin_call(groups.size() + singles.size() == 1 ? last_path : ELPA_PATH_AUTO);
   const int cus = device_cus();
-  for (auto& kv : groups) {
-    const ehh::StripeEntry* se = entry[kv.first];
-    const hipError_t err = se->batched(probs, kv.second.data(), (int64_t)kv.second.size(),
+  for (const ehh::StripeEntry* se : order) {
+    const std::vector<int64_t>& ids = groups[se];
+    const hipError_t err = se->batched(probs, ids.data(), (int64_t)ids.size(),
                                        tile_opts(plan), st, cus);
     if (err != hipSuccess) return ELPA_ERR_DEVICE;
   }

@@ -47,6 +47,9 @@ const StripeEntry* split_table(int* size);   // two lanes per column, packed ref
 const StripeEntry* wy_table(int* size);      // compact-WY sub-groups on MFMA
 RefLaunch ref_launcher(int dtype);
 
+// Tuned plan of the size class of (n, nev), if the tuner holds one.
+bool tuner_lookup(int32_t dtype, int64_t nbw, int64_t n, int64_t nev, elpa_hh_plan* out);
+
 // Timing of the main kernel sequence (the tile launches of the stripe paths,
 // the single launch of the reference path) of the latest call made on the
 // calling host thread, while enabled with elpa_hh_profile_enable: an event

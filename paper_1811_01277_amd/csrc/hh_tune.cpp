@@ -1,0 +1,223 @@
+// Plan tuner of the tridiagonal->band back-transformation (C ABI in
+// include/elpa_hh.h): a per-process cache of measured plans keyed by
+// (element type, nbw, size class of n, size class of nev), the measurement
+// that fills it, and its text save / load.
+//
+// The tuned parameters are the kernel family (one-lane stripe, two-lane
+// stripe, compact-WY MFMA), the sweeps fused per pass k (the reflector
+// grouping), the chase steps per tile (the stripe tile height) and the number
+// of stripe-group streams.  Calls without an explicit plan use the cached
+// plan of their size class when there is one.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
+#include "../../include/elpa_hh.h"
+#include "hh_dispatch.h"
+
+namespace ehh {
+
+namespace {
+
+// size class: quarter octaves (sizes within ~19 % share a class)
+int64_t size_class(int64_t x) {
+  if (x < 1) return 0;
+  return (int64_t)std::floor(4.0 * std::log2((double)x) + 1e-9);
+}
+
+using Key = std::tuple<int32_t, int64_t, int64_t, int64_t>;
+
+struct Cache {
+  std::mutex mu;
+  std::map<Key, elpa_hh_plan> plans;
+  static Cache& get() {
+    static Cache c;
+    return c;
+  }
+};
+
+Key key_of(int32_t dtype, int64_t nbw, int64_t n, int64_t nev) {
+  return Key{dtype, nbw, size_class(n), size_class(nev)};
+}
+
+bool plan_valid(const elpa_hh_plan& p) {
+  return p.path >= ELPA_PATH_AUTO && p.path <= ELPA_PATH_WY && p.k >= 0 && p.steps >= 0 &&
+         p.order >= ELPA_ORDER_AUTO && p.order <= ELPA_ORDER_XCD && p.streams >= 0 &&
+         p.streams <= 8 && p.reserved == 0;
+}
+
+}  // namespace
+
+bool tuner_lookup(int32_t dtype, int64_t nbw, int64_t n, int64_t nev, elpa_hh_plan* out) {
+  Cache& c = Cache::get();
+  std::lock_guard<std::mutex> g(c.mu);
+  const auto it = c.plans.find(key_of(dtype, nbw, n, nev));
+  if (it == c.plans.end()) return false;
+  *out = it->second;
+  return true;
+}
+
+}  // namespace ehh
+
+extern "C" {
+
+int elpa_hh_tuner_set(int32_t dtype, int64_t nbw, int64_t n, int64_t nev,
+                      const elpa_hh_plan* plan) {
+  if (!plan || nbw < 1 || n < 0 || nev < 0 || !ehh::plan_valid(*plan)) return ELPA_ERR_ARG;
+  if (!elpa_hh_plan_supported(nbw, dtype, plan)) return ELPA_ERR_PLAN;
+  ehh::Cache& c = ehh::Cache::get();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.plans[ehh::key_of(dtype, nbw, n, nev)] = *plan;
+  return ELPA_OK;
+}
+
+int elpa_hh_tuner_get(int32_t dtype, int64_t nbw, int64_t n, int64_t nev, elpa_hh_plan* out) {
+  if (!out) return ELPA_ERR_ARG;
+  return ehh::tuner_lookup(dtype, nbw, n, nev, out) ? 1 : 0;
+}
+
+int64_t elpa_hh_tuner_size(void) {
+  ehh::Cache& c = ehh::Cache::get();
+  std::lock_guard<std::mutex> g(c.mu);
+  return (int64_t)c.plans.size();
+}
+
+void elpa_hh_tuner_clear(void) {
+  ehh::Cache& c = ehh::Cache::get();
+  std::lock_guard<std::mutex> g(c.mu);
+  c.plans.clear();
+}
+
+int elpa_hh_tuner_save(const char* path) {
+  if (!path) return ELPA_ERR_ARG;
+  ehh::Cache& c = ehh::Cache::get();
+  std::lock_guard<std::mutex> g(c.mu);
+  FILE* f = std::fopen(path, "w");
+  if (!f) return ELPA_ERR_ARG;
+  std::fprintf(f, "elpa_hh_tuner 1\n");
+  std::fprintf(f, "# dtype nbw n_class nev_class path k steps order streams\n");
+  for (const auto& kv : c.plans) {
+    const elpa_hh_plan& p = kv.second;
+    std::fprintf(f, "%d %lld %lld %lld %d %d %d %d %d\n", (int)std::get<0>(kv.first),
+                 (long long)std::get<1>(kv.first), (long long)std::get<2>(kv.first),
+                 (long long)std::get<3>(kv.first), p.path, p.k, p.steps, p.order, p.streams);
+  }
+  const bool ok = std::fclose(f) == 0;
+  return ok ? ELPA_OK : ELPA_ERR_ARG;
+}
+
+int elpa_hh_tuner_load(const char* path) {
+  if (!path) return ELPA_ERR_ARG;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return ELPA_ERR_ARG;
+  char line[512];
+  std::map<ehh::Key, elpa_hh_plan> got;
+  bool ok = std::fgets(line, sizeof line, f) && std::strncmp(line, "elpa_hh_tuner 1", 15) == 0;
+  while (ok && std::fgets(line, sizeof line, f)) {
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int dt, path_, k, steps, order, streams;
+    long long nbw, nc, ec;
+    if (std::sscanf(line, "%d %lld %lld %lld %d %d %d %d %d", &dt, &nbw, &nc, &ec, &path_, &k,
+                    &steps, &order, &streams) != 9) {
+      ok = false;
+      break;
+    }
+    const elpa_hh_plan p{path_, k, steps, order, streams, 0};
+    if (nbw < 1 || nc < 0 || ec < 0 || !ehh::plan_valid(p) ||
+        !elpa_hh_plan_supported(nbw, dt, &p)) {
+      ok = false;
+      break;
+    }
+    got[ehh::Key{dt, (int64_t)nbw, (int64_t)nc, (int64_t)ec}] = p;
+  }
+  std::fclose(f);
+  if (!ok) return ELPA_ERR_ARG;
+  ehh::Cache& c = ehh::Cache::get();
+  std::lock_guard<std::mutex> g(c.mu);
+  for (const auto& kv : got) c.plans[kv.first] = kv.second;
+  return ELPA_OK;
+}
+
+int elpa_hh_tune(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau,
+                 const void* Q, int64_t ldq, int32_t dtype, void* stream, int32_t level,
+                 elpa_hh_plan* best) {
+  if (level < 0 || level > 2) return ELPA_ERR_ARG;
+  if (n <= 1 || nev <= 0 || nbw < 1 || ldq < n || !hh || !tau || !Q) return ELPA_ERR_ARG;
+  if (dtype != ELPA_R64 && dtype != ELPA_R32 && dtype != ELPA_C64) return ELPA_ERR_DTYPE;
+  const int64_t es = dtype == ELPA_C64 ? 16 : (dtype == ELPA_R32 ? 4 : 8);
+  // candidates: level 0 each kernel family's default k, level 1 every compiled
+  // k, level 2 also explicit tile heights; each with 1 and 2 stripe groups
+  std::vector<elpa_hh_plan> cand;
+  const int steps_list[] = {0, 2, 4, 8, 16};
+  const int nsteps = level == 2 ? 5 : 1;
+  for (int fam : {ELPA_PATH_SPLIT, ELPA_PATH_WY, ELPA_PATH_STRIPE}) {
+    std::vector<int> ks;
+    if (level == 0) {
+      const elpa_hh_plan def{fam, 0, 0, 0, 0, 0};
+      if (elpa_hh_plan_supported(nbw, dtype, &def)) ks.push_back(0);
+    } else {
+      int cnt = 0;
+      const ehh::StripeEntry* tab = fam == ELPA_PATH_SPLIT ? ehh::split_table(&cnt)
+                                    : fam == ELPA_PATH_WY  ? ehh::wy_table(&cnt)
+                                                           : ehh::stripe_table(&cnt);
+      for (int i = 0; i < cnt; ++i)
+        if (tab[i].dtype == dtype && tab[i].nb == nbw) ks.push_back(tab[i].k);
+    }
+    for (int k : ks)
+      for (int si = 0; si < nsteps; ++si)
+        for (int streams : {1, 2}) cand.push_back(elpa_hh_plan{fam, k, steps_list[si], 0, streams, 0});
+  }
+  if (cand.empty()) cand.push_back(elpa_hh_plan{ELPA_PATH_REF, 0, 0, 0, 0, 0});
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  void* scratch = nullptr;
+  // the caller's Q spans ldq*(nev-1) + n elements
+  const size_t bytes = ((size_t)ldq * (size_t)(nev - 1) + (size_t)n) * (size_t)es;
+  if (hipMallocAsync(&scratch, bytes, st) != hipSuccess) return ELPA_ERR_NOMEM;
+  hipEvent_t a = nullptr, b = nullptr;
+  bool ok = hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess &&
+            hipMemcpyAsync(scratch, Q, bytes, hipMemcpyDeviceToDevice, st) == hipSuccess;
+  float best_ms = -1.f;
+  elpa_hh_plan win{};
+  const int reps = 2;
+  int rc = ELPA_OK;
+  for (size_t i = 0; ok && i < cand.size(); ++i) {
+    const elpa_hh_plan& p = cand[i];
+    // warm-up (also the first use of the kernel, and the argument checks)
+    rc = elpa_hh_trafo_plan(n, nev, nbw, hh, tau, scratch, ldq, dtype, stream, &p);
+    if (rc != ELPA_OK) {
+      ok = false;
+      break;
+    }
+    ok = hipEventRecord(a, st) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r)
+      ok = elpa_hh_trafo_plan(n, nev, nbw, hh, tau, scratch, ldq, dtype, stream, &p) == ELPA_OK;
+    ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, a, b) == hipSuccess;
+    if (ok && (best_ms < 0.f || ms < best_ms)) {
+      best_ms = ms;
+      win = p;
+    }
+  }
+  (void)hipFreeAsync(scratch, st);
+  (void)hipStreamSynchronize(st);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (rc != ELPA_OK) return rc;
+  if (!ok || best_ms < 0.f) return ELPA_ERR_DEVICE;
+  {
+    ehh::Cache& c = ehh::Cache::get();
+    std::lock_guard<std::mutex> g(c.mu);
+    c.plans[ehh::key_of(dtype, nbw, n, nev)] = win;
+  }
+  if (best) *best = win;
+  return ELPA_OK;
+}
+
+}  // extern "C"

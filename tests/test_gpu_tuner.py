@@ -1,0 +1,92 @@
+"""GPU tests of the plan tuner: elpa_hh_tune leaves Q untouched and caches a
+runnable plan; calls without a plan then run it; a batch whose problems have
+plans with different kernels runs them as separate launch sequences with the
+same results as single calls."""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import bt, checks
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import time
+    t0 = time.time()
+    print("importing torch", flush=True)
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_01277_amd as P
+    P.library()
+    print(f"torch ready after {time.time() - t0:.1f} s", flush=True)
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(autouse=True)
+def clean():
+    import paper_1811_01277_amd as P
+    P.tuner_clear()
+    yield
+    P.tuner_clear()
+
+
+def make(torch, dev, n, nbw, nev, seed):
+    hh, tau = W.synthetic_reflectors(n, nbw, seed=seed)
+    Z = np.asfortranarray(W.gaussian_block(n, nev, seed=seed + 1))
+    q = torch.from_numpy(np.ascontiguousarray(Z.T)).to(dev).t()
+    return q, torch.from_numpy(hh).to(dev), torch.from_numpy(tau).to(dev), (hh, tau, Z)
+
+
+@pytest.mark.parametrize("level", [0, 1])
+def test_tune_keeps_q_and_plan_is_used(torch_dev, level):
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 700, 64, 300
+    q, h, t, (hh, tau, Z) = make(torch, dev, n, nbw, nev, 1100 + level)
+    before = q.clone()
+    print(f"tune level {level}", flush=True)
+    plan = P.tune(q, h, t, nbw, level=level)
+    torch.cuda.synchronize()
+    print("tuned plan", plan, flush=True)
+    assert torch.equal(q, before), "tuning modified Q"
+    assert P.tuner_get(P.R64, nbw, n, nev) == plan
+    assert P.plan_supported(nbw, P.R64, plan["path"], plan["k"])
+    P.profile_enable(True)
+    try:
+        P.hh_trafo(q, h, t, nbw)                 # no plan: the tuned one
+        pr = P.profile_last()
+    finally:
+        P.profile_enable(False)
+    assert pr["path"] == plan["path"]
+    if plan["k"]:
+        assert pr["k"] == plan["k"]
+    assert pr["streams"] == (plan["streams"] or 2)
+    ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
+    assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12
+
+
+def test_batch_with_tuned_plans_of_different_kernels(torch_dev):
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    # two size classes with different k: two launch sequences in one call
+    P.tuner_set(P.R64, 64, 300, 300, path=P.PATH_SPLIT, k=48)
+    P.tuner_set(P.R64, 64, 900, 900, path=P.PATH_SPLIT, k=80)
+    sizes = [300, 900, 290, 880]      # size classes floor(4 log2 n): 32, 39, 32, 39
+    probs, host, singles = [], [], []
+    for i, n in enumerate(sizes):
+        q, h, t, hst = make(torch, dev, n, 64, n, 1200 + i)
+        probs.append((q, h, t, 64))
+        host.append(hst)
+    for (q, h, t, nbw) in probs:
+        qq = q.clone()
+        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT,
+                   k=P.tuner_get(P.R64, 64, q.shape[0], q.shape[1])["k"])
+        singles.append(qq)
+    P.hh_trafo_batched(probs)
+    torch.cuda.synchronize()
+    for (q, _, _, _), s, (hh, tau, Z), n in zip(probs, singles, host, sizes):
+        assert torch.equal(q, s)
+        ref = bt.bt_tridiag_to_band(hh, tau, Z, n, 64)
+        assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12

@@ -1,0 +1,78 @@
+"""Plan tuner cache (CPU): explicit entries, size classes, save / load round
+trip, refusal of malformed files and of plans that cannot run."""
+import os
+
+import pytest
+
+import paper_1811_01277_amd as P
+
+
+@pytest.fixture(autouse=True)
+def clean():
+    P.tuner_clear()
+    yield
+    P.tuner_clear()
+
+
+def test_set_get_size_classes():
+    assert P.tuner_size() == 0 and P.tuner_get(P.R64, 64, 20000, 20000) is None
+    P.tuner_set(P.R64, 64, 20000, 20000, path=P.PATH_SPLIT, k=64, steps=8, streams=2)
+    got = P.tuner_get(P.R64, 64, 20000, 20000)
+    assert got == {"path": P.PATH_SPLIT, "k": 64, "steps": 8, "order": 0, "streams": 2}
+    # quarter-octave classes: 4 log2(20000) = 57.15, [19504, 23193) shares it
+    assert P.tuner_get(P.R64, 64, 21000, 19600) == got
+    assert P.tuner_get(P.R64, 64, 24000, 20000) is None
+    assert P.tuner_get(P.R64, 32, 20000, 20000) is None          # other nbw
+    assert P.tuner_get(P.R32, 64, 20000, 20000) is None          # other dtype
+    assert P.tuner_size() == 1
+    P.tuner_set(P.R64, 64, 20500, 20000, path=P.PATH_SPLIT, k=80)  # same class: replaced
+    assert P.tuner_size() == 1 and P.tuner_get(P.R64, 64, 20000, 20000)["k"] == 80
+
+
+def test_set_refuses_plans_that_cannot_run():
+    with pytest.raises(P.ElpaError) as e:
+        P.tuner_set(P.R64, 64, 1000, 1000, path=P.PATH_SPLIT, k=63)
+    assert e.value.code == -6
+    with pytest.raises(P.ElpaError) as e:
+        P.tuner_set(P.C64, 64, 1000, 1000, path=P.PATH_WY)
+    assert e.value.code == -6
+    with pytest.raises(P.ElpaError) as e:
+        P.tuner_set(P.R64, 64, 1000, 1000, path=P.PATH_SPLIT, k=64, streams=9)
+    assert e.value.code == -1
+    assert P.tuner_size() == 0
+
+
+def test_save_load_round_trip(tmp_path):
+    P.tuner_set(P.R64, 64, 20000, 2000, path=P.PATH_SPLIT, k=80, steps=2, streams=2)
+    P.tuner_set(P.R32, 64, 20000, 2000, path=P.PATH_WY, k=64)
+    P.tuner_set(P.C64, 64, 8192, 8192, path=P.PATH_STRIPE, k=4, order=P.ORDER_XCD)
+    f = tmp_path / "plans.txt"
+    P.tuner_save(str(f))
+    text = f.read_text().splitlines()
+    assert text[0] == "elpa_hh_tuner 1" and len([l for l in text if not l.startswith("#")]) == 4
+    before = {k: P.tuner_get(*k) for k in [(P.R64, 64, 20000, 2000), (P.R32, 64, 20000, 2000),
+                                           (P.C64, 64, 8192, 8192)]}
+    P.tuner_clear()
+    assert P.tuner_size() == 0
+    P.tuner_load(str(f))
+    assert P.tuner_size() == 3
+    for k, v in before.items():
+        assert P.tuner_get(*k) == v
+
+
+@pytest.mark.parametrize("body", [
+    "not a tuner file\n",
+    "elpa_hh_tuner 1\n0 64 57 57 3 64 8 0\n",            # a field missing
+    "elpa_hh_tuner 1\n0 64 57 57 3 63 8 0 2\n",          # no k = 63 kernel
+    "elpa_hh_tuner 1\n0 64 57 57 9 64 8 0 2\n",          # no such path
+])
+def test_load_refuses_bad_files_whole(tmp_path, body):
+    P.tuner_set(P.R64, 64, 100, 100, path=P.PATH_REF)
+    f = tmp_path / "bad.txt"
+    f.write_text(body)
+    with pytest.raises(P.ElpaError) as e:
+        P.tuner_load(str(f))
+    assert e.value.code == -1
+    assert P.tuner_size() == 1                           # cache unchanged
+    with pytest.raises(P.ElpaError):
+        P.tuner_load(os.path.join(str(tmp_path), "missing.txt"))
