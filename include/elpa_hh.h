@@ -71,7 +71,7 @@ enum {
                              per column (all element types) */
     ELPA_PATH_SPLIT = 3,  /* register-window stripe kernel, k sweeps fused, two lanes
                              per column and reflectors pre-packed in consumption order
-                             (real fp64, nbw 32 or 64; the fp64 default) */
+                             (real and complex fp64, nbw 32 or 64; their default) */
     ELPA_PATH_WY = 4      /* compact-WY aggregation of 16 reflectors at a time,
                              applied by MFMA tiles to an LDS-resident window (real fp64
                              and fp32, nbw 32 or 64; the fp32 default) */

@@ -38,7 +38,7 @@ const ehh::StripeEntry* find_entry(int path, int32_t dtype, int64_t nb, int k) {
 // Library default of the sweeps fused per pass, per kernel family: the first
 // compiled entry in order of preference (0 if none).
 int default_k(int path, int32_t dtype, int64_t nb) {
-  static const int split_pref[] = {80, 64, 48, 32, 96};
+  static const int split_pref[] = {80, 64, 48, 32, 96, 24, 16};
   static const int wy_pref[] = {64, 48, 32, 96};
   static const int stripe_pref[] = {32, 16, 8, 4};
   static const int stripe_pref_c[] = {4, 2};

@@ -14,6 +14,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "hh_common.h"
+
 namespace ehh {
 
 // the broadcast lane is an immediate asm operand (operand number N)
@@ -172,6 +174,185 @@ __device__ __forceinline__ void supd2_b(double* x, double* y, double* xe, double
     asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 16, 17, 18, EHH_LB)
                  : EHH_PX8(x), EHH_PX8(y)
                  : "v"(V0), "v"(V1), "v"(nw));
+}
+
+// ---------------------------------------------------------------------------
+// Complex (fp64 pairs) split-window blocks.  One segment, broadcast lanes
+// l0..l0+7: dot  a += conj(v) x  (4 FMAs per value, the -Im v term through the
+// DPP source's negation modifier); update  x += v nw  (nw = -tau a, 4 FMAs).
+// Operands: dot %0 a.re, %1 a.im, %2 V.re, %3 V.im, %4.. x[k].re, x[k].im;
+// update %0.. x[k].re, x[k].im, then V.re, V.im, nw.re, nw.im.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void cdot_a(double& ar, double& ai, double Vr, double Vi,
+                                       const z64* x) {
+  asm volatile("s_nop 1\n"
+               "v_fmac_f64_dpp %0, %2, %4 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %7 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %7 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %6 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %8 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %9 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %9 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %8 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %10 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %11 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %11 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %10 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %12 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %13 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %13 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %12 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %14 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %15 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %15 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %14 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %16 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %17 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %17 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %16 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %18 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %19 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %19 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %18 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               : "+v"(ar), "+v"(ai)
+               : "v"(Vr), "v"(Vi), "v"(x[0].re), "v"(x[0].im), "v"(x[1].re), "v"(x[1].im), "v"(x[2].re), "v"(x[2].im), "v"(x[3].re), "v"(x[3].im), "v"(x[4].re), "v"(x[4].im), "v"(x[5].re), "v"(x[5].im), "v"(x[6].re), "v"(x[6].im), "v"(x[7].re), "v"(x[7].im));
+}
+__device__ __forceinline__ void cupd_a(z64* x, double Vr, double Vi, double nr,
+                                       double ni) {
+  asm volatile("s_nop 1\n"
+               "v_fmac_f64_dpp %0, %16, %18 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %16, %19 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, -%17, %19 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %17, %18 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %2, %16, %18 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %3, %16, %19 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %2, -%17, %19 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %3, %17, %18 row_newbcast:1 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %4, %16, %18 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %5, %16, %19 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %4, -%17, %19 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %5, %17, %18 row_newbcast:2 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %6, %16, %18 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %7, %16, %19 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %6, -%17, %19 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %7, %17, %18 row_newbcast:3 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %8, %16, %18 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %9, %16, %19 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %8, -%17, %19 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %9, %17, %18 row_newbcast:4 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %10, %16, %18 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %11, %16, %19 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %10, -%17, %19 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %11, %17, %18 row_newbcast:5 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %12, %16, %18 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %13, %16, %19 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %12, -%17, %19 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %13, %17, %18 row_newbcast:6 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %14, %16, %18 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %15, %16, %19 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %14, -%17, %19 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %15, %17, %18 row_newbcast:7 row_mask:0xf bank_mask:0xf\n"
+               : "+v"(x[0].re), "+v"(x[0].im), "+v"(x[1].re), "+v"(x[1].im), "+v"(x[2].re), "+v"(x[2].im), "+v"(x[3].re), "+v"(x[3].im), "+v"(x[4].re), "+v"(x[4].im), "+v"(x[5].re), "+v"(x[5].im), "+v"(x[6].re), "+v"(x[6].im), "+v"(x[7].re), "+v"(x[7].im)
+               : "v"(Vr), "v"(Vi), "v"(nr), "v"(ni));
+}
+__device__ __forceinline__ void cdot_b(double& ar, double& ai, double Vr, double Vi,
+                                       const z64* x) {
+  asm volatile("s_nop 1\n"
+               "v_fmac_f64_dpp %0, %2, %4 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %5 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %5 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %6 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %7 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %7 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %6 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %8 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %9 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %9 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %8 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %10 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %11 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %11 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %10 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %12 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %13 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %13 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %12 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %14 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %15 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %14 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %17 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %17 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %16 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %2, %18 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %19 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %19 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %18 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               : "+v"(ar), "+v"(ai)
+               : "v"(Vr), "v"(Vi), "v"(x[0].re), "v"(x[0].im), "v"(x[1].re), "v"(x[1].im), "v"(x[2].re), "v"(x[2].im), "v"(x[3].re), "v"(x[3].im), "v"(x[4].re), "v"(x[4].im), "v"(x[5].re), "v"(x[5].im), "v"(x[6].re), "v"(x[6].im), "v"(x[7].re), "v"(x[7].im));
+}
+__device__ __forceinline__ void cupd_b(z64* x, double Vr, double Vi, double nr,
+                                       double ni) {
+  asm volatile("s_nop 1\n"
+               "v_fmac_f64_dpp %0, %16, %18 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %16, %19 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, -%17, %19 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %17, %18 row_newbcast:8 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %2, %16, %18 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %3, %16, %19 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %2, -%17, %19 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %3, %17, %18 row_newbcast:9 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %4, %16, %18 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %5, %16, %19 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %4, -%17, %19 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %5, %17, %18 row_newbcast:10 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %6, %16, %18 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %7, %16, %19 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %6, -%17, %19 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %7, %17, %18 row_newbcast:11 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %8, %16, %18 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %9, %16, %19 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %8, -%17, %19 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %9, %17, %18 row_newbcast:12 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %10, %16, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %11, %16, %19 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %10, -%17, %19 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %11, %17, %18 row_newbcast:13 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %12, %16, %18 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %13, %16, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %12, -%17, %19 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %13, %17, %18 row_newbcast:14 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %14, %16, %18 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %15, %16, %19 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %14, -%17, %19 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %15, %17, %18 row_newbcast:15 row_mask:0xf bank_mask:0xf\n"
+               : "+v"(x[0].re), "+v"(x[0].im), "+v"(x[1].re), "+v"(x[1].im), "+v"(x[2].re), "+v"(x[2].im), "+v"(x[3].re), "+v"(x[3].im), "+v"(x[4].re), "+v"(x[4].im), "+v"(x[5].re), "+v"(x[5].im), "+v"(x[6].re), "+v"(x[6].im), "+v"(x[7].re), "+v"(x[7].im)
+               : "v"(Vr), "v"(Vi), "v"(nr), "v"(ni));
+}
+// extra term of an odd window offset: lane 0 of the third segment
+__device__ __forceinline__ void cdot_x(double& ar, double& ai, double Vr, double Vi, const z64& x) {
+  asm volatile("s_nop 1\n"
+               "v_fmac_f64_dpp %0, %2, %4 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, %3, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, -%3, %4 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               : "+v"(ar), "+v"(ai)
+               : "v"(Vr), "v"(Vi), "v"(x.re), "v"(x.im));
+}
+__device__ __forceinline__ void cupd_x(z64& x, double Vr, double Vi, double nr, double ni) {
+  asm volatile("s_nop 1\n"
+               "v_fmac_f64_dpp %0, %2, %4 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %2, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %0, -%3, %5 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               "v_fmac_f64_dpp %1, %3, %4 row_newbcast:0 row_mask:0xf bank_mask:0xf\n"
+               : "+v"(x.re), "+v"(x.im)
+               : "v"(Vr), "v"(Vi), "v"(nr), "v"(ni));
 }
 
 }  // namespace ehh

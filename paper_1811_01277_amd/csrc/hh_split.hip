@@ -1,4 +1,4 @@
-// Split-window stripe kernel (real fp64) of the tridiagonal->band eigenvector
+// Split-window stripe kernel (real and complex fp64) of the tridiagonal->band eigenvector
 // back-transformation  Q <- H(0,0) H(0,1) ... H(n-2, J-1) Q  (Kus et al.,
 // Sec. 2 and Sec. 3.1).
 //
@@ -49,22 +49,22 @@ struct SplitGeom {
 };
 
 // Packed record of reflector (s0+o, j), o = 0..K-1, written by one block.
-template <int NB, int K>
-__device__ __forceinline__ void pack_group(const double* __restrict__ hh,
-                                           const double* __restrict__ tau, int64_t n, int64_t m,
-                                           int64_t j, int64_t Jmax, double* __restrict__ P) {
+template <typename E, int NB, int K>
+__device__ __forceinline__ void pack_group(const E* __restrict__ hh, const E* __restrict__ tau,
+                                           int64_t n, int64_t m, int64_t j, int64_t Jmax,
+                                           E* __restrict__ P) {
   using Gm = SplitGeom<NB, K>;
   const int64_t s0 = m * K;
   const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
   if (j >= J0) return;  // never read
   const int64_t ctot = csum(n - 1, NB);
-  double* __restrict__ rec = P + ((m * Jmax + j) * K) * Gm::RS;
+  E* __restrict__ rec = P + ((m * Jmax + j) * K) * Gm::RS;
   for (int e = (int)threadIdx.x; e < K * Gm::RS; e += (int)blockDim.x) {
     const int o = e / Gm::RS, rem = e - o * Gm::RS;
     const int h = rem / Gm::HS, t = rem - h * Gm::HS;
     const int64_t s = s0 + o;
     const bool valid = (s <= n - 2) && (j < (n - 1 - s + NB - 1) / NB);
-    double v = 0.0;
+    E v{};
     if (valid) {
       const int64_t slot = ctot - csum(n - 1 - s, NB) + j;
       if (h == 0 && t == Gm::HS - 1) {
@@ -80,53 +80,53 @@ __device__ __forceinline__ void pack_group(const double* __restrict__ hh,
   }
 }
 
-template <int NB, int K>
-__global__ __launch_bounds__(256) void k_pack_split(const double* __restrict__ hh,
-                                                    const double* __restrict__ tau, int64_t n,
-                                                    int64_t Jmax, double* __restrict__ P) {
+template <typename E, int NB, int K>
+__global__ __launch_bounds__(256) void k_pack_split(const E* __restrict__ hh,
+                                                    const E* __restrict__ tau, int64_t n,
+                                                    int64_t Jmax, E* __restrict__ P) {
   const int64_t g = blockIdx.x;
-  pack_group<NB, K>(hh, tau, n, g / Jmax, g % Jmax, Jmax, P);
+  pack_group<E, NB, K>(hh, tau, n, g / Jmax, g % Jmax, Jmax, P);
 }
 
-template <int NB, int K>
+template <typename E, int NB, int K>
 __global__ __launch_bounds__(256) void k_pack_split_b(const ProblemDesc* __restrict__ d,
                                                       int count) {
   const int b = (int)blockIdx.x;
   const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::ptile0>(d, count, b)];
   const int64_t g = b - D.ptile0;
-  pack_group<NB, K>((const double*)D.hh, (const double*)D.tau, D.n, g / D.Jmax, g % D.Jmax,
-                    D.Jmax, (double*)D.P);
+  pack_group<E, NB, K>((const E*)D.hh, (const E*)D.tau, D.n, g / D.Jmax, g % D.Jmax, D.Jmax,
+                       (E*)D.P);
 }
 
 // Layout conversion between Q (column major) and SW-column stripes, element
 // (r, SW*c + l) at Qs[(c*rows_pad + r)*SW + l]; 64 x 64 tiles through LDS,
 // padding rows and columns written as zeros.
-template <int SW>
-__device__ __forceinline__ void to_rows_tile_sw(const double* __restrict__ Q, int64_t ldq,
-                                                int64_t n, int64_t nev, double* __restrict__ Qs,
+template <typename E, int SW>
+__device__ __forceinline__ void to_rows_tile_sw(const E* __restrict__ Q, int64_t ldq,
+                                                int64_t n, int64_t nev, E* __restrict__ Qs,
                                                 int64_t rows_pad, int64_t G, int64_t rt,
-                                                int64_t ct, double (*tile)[65]) {
+                                                int64_t ct, E (*tile)[65]) {
   const int64_t r0 = rt * 64, c0 = ct * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   for (int cc = ty; cc < 64; cc += 4) {
     const int64_t r = r0 + tx, col = c0 + cc;
-    tile[cc][tx] = (r < n && col < nev) ? Q[r + col * ldq] : 0.0;
+    tile[cc][tx] = (r < n && col < nev) ? Q[r + col * ldq] : E{};
   }
   __syncthreads();
   const int64_t col = c0 + tx, c = col / SW, l = col - c * SW;
   if (c >= G) return;
-  double* __restrict__ dst = Qs + c * rows_pad * SW + l;
+  E* __restrict__ dst = Qs + c * rows_pad * SW + l;
   for (int rr = ty; rr < 64; rr += 4) {
     const int64_t r = r0 + rr;
     if (r < rows_pad) dst[r * SW] = tile[tx][rr];
   }
 }
 
-template <int SW>
-__device__ __forceinline__ void from_rows_tile_sw(const double* __restrict__ Qs, int64_t rows_pad,
-                                                  double* __restrict__ Q, int64_t ldq, int64_t n,
+template <typename E, int SW>
+__device__ __forceinline__ void from_rows_tile_sw(const E* __restrict__ Qs, int64_t rows_pad,
+                                                  E* __restrict__ Q, int64_t ldq, int64_t n,
                                                   int64_t nev, int64_t G, int64_t rt, int64_t ct,
-                                                  double (*tile)[65]) {
+                                                  E (*tile)[65]) {
   const int64_t r0 = rt * 64, c0 = ct * 64;
   const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
   {
@@ -143,43 +143,43 @@ __device__ __forceinline__ void from_rows_tile_sw(const double* __restrict__ Qs,
   }
 }
 
-template <int SW>
-__global__ __launch_bounds__(256) void k_to_rows_sw(const double* __restrict__ Q, int64_t ldq,
+template <typename E, int SW>
+__global__ __launch_bounds__(256) void k_to_rows_sw(const E* __restrict__ Q, int64_t ldq,
                                                     int64_t n, int64_t nev,
-                                                    double* __restrict__ Qs, int64_t rows_pad,
+                                                    E* __restrict__ Qs, int64_t rows_pad,
                                                     int64_t G) {
-  __shared__ double tile[64][65];
-  to_rows_tile_sw<SW>(Q, ldq, n, nev, Qs, rows_pad, G, blockIdx.x, blockIdx.y, tile);
+  __shared__ E tile[64][65];
+  to_rows_tile_sw<E, SW>(Q, ldq, n, nev, Qs, rows_pad, G, blockIdx.x, blockIdx.y, tile);
 }
 
-template <int SW>
-__global__ __launch_bounds__(256) void k_from_rows_sw(const double* __restrict__ Qs,
-                                                      int64_t rows_pad, double* __restrict__ Q,
+template <typename E, int SW>
+__global__ __launch_bounds__(256) void k_from_rows_sw(const E* __restrict__ Qs,
+                                                      int64_t rows_pad, E* __restrict__ Q,
                                                       int64_t ldq, int64_t n, int64_t nev,
                                                       int64_t G) {
-  __shared__ double tile[64][65];
-  from_rows_tile_sw<SW>(Qs, rows_pad, Q, ldq, n, nev, G, blockIdx.x, blockIdx.y, tile);
+  __shared__ E tile[64][65];
+  from_rows_tile_sw<E, SW>(Qs, rows_pad, Q, ldq, n, nev, G, blockIdx.x, blockIdx.y, tile);
 }
 
-template <int SW>
+template <typename E, int SW>
 __global__ __launch_bounds__(256) void k_to_rows_sw_b(const ProblemDesc* __restrict__ d,
                                                       int count) {
-  __shared__ double tile[64][65];
+  __shared__ E tile[64][65];
   const int t = (int)blockIdx.x;
   const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::tile0>(d, count, t)];
   const int local = t - D.tile0;
-  to_rows_tile_sw<SW>((const double*)D.Q, D.ldq, D.n, D.nev, (double*)D.Qs, D.rows_pad, D.G,
+  to_rows_tile_sw<E, SW>((const E*)D.Q, D.ldq, D.n, D.nev, (E*)D.Qs, D.rows_pad, D.G,
                       local / D.GT, local % D.GT, tile);
 }
 
-template <int SW>
+template <typename E, int SW>
 __global__ __launch_bounds__(256) void k_from_rows_sw_b(const ProblemDesc* __restrict__ d,
                                                         int count) {
-  __shared__ double tile[64][65];
+  __shared__ E tile[64][65];
   const int t = (int)blockIdx.x;
   const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::otile0>(d, count, t)];
   const int local = t - D.otile0;
-  from_rows_tile_sw<SW>((const double*)D.Qs, D.rows_pad, (double*)D.Q, D.ldq, D.n, D.nev, D.G,
+  from_rows_tile_sw<E, SW>((const E*)D.Qs, D.rows_pad, (E*)D.Q, D.ldq, D.n, D.nev, D.G,
                         local / D.GT, local % D.GT, tile);
 }
 
@@ -262,26 +262,96 @@ __device__ __forceinline__ void step_split(double (&x)[R], const double* __restr
   });
 }
 
+// Complex counterpart: record values are complex (re, im), reflector o's
+// dot product conj(v)^T x and update x += v nw with nw = -tau (dot), each
+// complex product as four fp64 FMAs with a broadcast reflector operand.
+struct SplitValsC {
+  z64 v0, v1, v2, t;
+};
+
+template <int NB, int K, int o>
+__device__ __forceinline__ SplitValsC split_load_c(const z64* __restrict__ Pj, int voff, int z) {
+  using Gm = SplitGeom<NB, K>;
+  const z64* __restrict__ rec = Pj + o * Gm::RS + z;
+  SplitValsC s;
+  s.v0 = rec[voff];
+  s.v1 = (Gm::NG == 2) ? rec[voff + 16] : z64{0.0, 0.0};
+  s.v2 = (o & 1) ? rec[voff + 16 * Gm::NG] : z64{0.0, 0.0};
+  s.t = rec[Gm::HS - 1];
+  return s;
+}
+
+template <int NB, int K, int PD, int R>
+__device__ __forceinline__ void step_split_c(z64 (&x)[R], const z64* __restrict__ Pj, int voff) {
+  using Gm = SplitGeom<NB, K>;
+  static_assert(R == Gm::R, "window register count");
+  static_assert(PD >= 1 && PD <= 4 && PD < K, "prefetch distance 1..4");
+  constexpr int HN = Gm::HN, NG = Gm::NG;
+  SplitValsC buf[PD];
+  FwdFor<PD>::run([&](auto ic) {
+    constexpr int i = decltype(ic)::value;
+    buf[i] = split_load_c<NB, K, K - 1 - i>(Pj, voff, 0);
+  });
+  RevFor<K>::run([&](auto oc) {
+    constexpr int o = decltype(oc)::value;
+    constexpr int p0 = o >> 1;
+    const SplitValsC c0 = buf[0];
+    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
+    if constexpr (NG == 2) {
+      cdot_a(a0r, a0i, c0.v0.re, c0.v0.im, &x[p0]);
+      cdot_a(a1r, a1i, c0.v1.re, c0.v1.im, &x[p0 + 16]);
+    } else {
+      cdot_a(a0r, a0i, c0.v0.re, c0.v0.im, &x[p0]);
+    }
+    SplitValsC nn{};
+    if constexpr (o - PD >= 0) nn = split_load_c<NB, K, o - PD>(Pj, voff, zero_after(a0r));
+    if constexpr (NG == 2) {
+      cdot_b(a0r, a0i, c0.v0.re, c0.v0.im, &x[p0 + 8]);
+      cdot_b(a1r, a1i, c0.v1.re, c0.v1.im, &x[p0 + 24]);
+    } else {
+      cdot_b(a1r, a1i, c0.v0.re, c0.v0.im, &x[p0 + 8]);
+    }
+    if constexpr ((o & 1) != 0) cdot_x(a0r, a0i, c0.v2.re, c0.v2.im, x[p0 + HN]);
+    const double tr = half_pair_sum(a0r + a1r), ti = half_pair_sum(a0i + a1i);
+    const double nr = -(c0.t.re * tr - c0.t.im * ti), ni = -(c0.t.re * ti + c0.t.im * tr);
+    if constexpr (NG == 2) {
+      cupd_a(&x[p0], c0.v0.re, c0.v0.im, nr, ni);
+      cupd_a(&x[p0 + 16], c0.v1.re, c0.v1.im, nr, ni);
+      cupd_b(&x[p0 + 8], c0.v0.re, c0.v0.im, nr, ni);
+      cupd_b(&x[p0 + 24], c0.v1.re, c0.v1.im, nr, ni);
+    } else {
+      cupd_a(&x[p0], c0.v0.re, c0.v0.im, nr, ni);
+      cupd_b(&x[p0 + 8], c0.v0.re, c0.v0.im, nr, ni);
+    }
+    if constexpr ((o & 1) != 0) cupd_x(x[p0 + HN], c0.v2.re, c0.v2.im, nr, ni);
+    FwdFor<PD - 1>::run([&](auto ic) {
+      constexpr int i = decltype(ic)::value;
+      buf[i] = buf[i + 1];
+    });
+    buf[PD - 1] = nn;
+  });
+}
+
 // One tile: group q (chase steps [qS, min(qS+S, J0))) of block m on stripe c.
 // Row pair (row0+2p, row0+2p+1) of the stripe is the 64 values at
 // Qs + (c*rows_pad + row0)*32 + 64p, lane l taking element l.
-template <int NB, int K, int PD>
-__device__ __forceinline__ void run_split_tile(const double* __restrict__ P, int64_t Jmax,
-                                               double* __restrict__ Qs, int64_t rows_pad,
+template <typename E, int NB, int K, int PD>
+__device__ __forceinline__ void run_split_tile(const E* __restrict__ P, int64_t Jmax,
+                                               E* __restrict__ Qs, int64_t rows_pad,
                                                int64_t n, int64_t c, int64_t m, int64_t q,
                                                int64_t S) {
   using Gm = SplitGeom<NB, K>;
   constexpr int R = Gm::R, HN = Gm::HN;
   const int lane = threadIdx.x;
   const int voff = (lane >> 5) * Gm::HS + (lane & 15);
-  double* __restrict__ bp = Qs + c * rows_pad * Gm::SW;
+  E* __restrict__ bp = Qs + c * rows_pad * Gm::SW;
   const int64_t s0 = m * K;
   const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
   const int64_t j0 = q * S;
   const int64_t j1 = (j0 + S < J0) ? j0 + S : J0;
-  double x[R];
+  E x[R];
   for (int64_t j = j0; j < j1; ++j) {
-    double* __restrict__ rp = bp + (s0 + 1 + j * NB) * Gm::SW;  // uniform
+    E* __restrict__ rp = bp + (s0 + 1 + j * NB) * Gm::SW;  // uniform
     if (j == j0) {
 #pragma unroll
       for (int p = 0; p < R; ++p) x[p] = rp[p * 64 + lane];
@@ -291,31 +361,34 @@ __device__ __forceinline__ void run_split_tile(const double* __restrict__ P, int
 #pragma unroll
       for (int p = R - HN; p < R; ++p) x[p] = rp[p * 64 + lane];
     }
-    step_split<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
+    if constexpr (std::is_same<E, double>::value)
+      step_split<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
+    else
+      step_split_c<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
 #pragma unroll
     for (int p = 0; p < HN; ++p) rp[p * 64 + lane] = x[p];
   }
   // window rows NB .. W-1 carried to the next group (or final); the extra row
   // W (upper half of the last register) is not written
-  double* __restrict__ rl = bp + (s0 + 1 + (j1 - 1) * NB) * Gm::SW;
+  E* __restrict__ rl = bp + (s0 + 1 + (j1 - 1) * NB) * Gm::SW;
 #pragma unroll
   for (int p = HN; p < R - 1; ++p) rl[p * 64 + lane] = x[p];
   if (lane < 32) rl[(R - 1) * 64 + lane] = x[R - 1];
 }
 
 // Stripes c0 .. c0+G-1 of the launch's blocks m0 .. m0+gridDim.x/G-1.
-template <int NB, int K, int OCC, int PD>
-__global__ __launch_bounds__(64, OCC) void k_split(const double* __restrict__ P, int64_t Jmax,
-                                                   double* __restrict__ Qs, int64_t rows_pad,
+template <typename E, int NB, int K, int OCC, int PD>
+__global__ __launch_bounds__(64, OCC) void k_split(const E* __restrict__ P, int64_t Jmax,
+                                                   E* __restrict__ Qs, int64_t rows_pad,
                                                    int64_t n, int c0, int G, int M, int t, int m0,
                                                    int S, int xcd) {
   const int b = tile_of((int)blockIdx.x, (int)gridDim.x, xcd);
   const int c = c0 + b % G;
   const int m = m0 + b / G;
-  run_split_tile<NB, K, PD>(P, Jmax, Qs, rows_pad, n, c, m, t - (M - 1 - m), S);
+  run_split_tile<E, NB, K, PD>(P, Jmax, Qs, rows_pad, n, c, m, t - (M - 1 - m), S);
 }
 
-template <int NB, int K, int OCC, int PD>
+template <typename E, int NB, int K, int OCC, int PD>
 __global__ __launch_bounds__(64, OCC) void k_split_b(const ProblemDesc* __restrict__ d,
                                                      const DiagEntry* __restrict__ e, int ecount,
                                                      int t, int xcd) {
@@ -324,40 +397,40 @@ __global__ __launch_bounds__(64, OCC) void k_split_b(const ProblemDesc* __restri
   const ProblemDesc& D = d[E0.p];
   const int local = b - E0.tile0;
   const int m = E0.m0 + local / D.G;
-  run_split_tile<NB, K, PD>((const double*)D.P, D.Jmax, (double*)D.Qs, D.rows_pad, D.n, local % D.G,
+  run_split_tile<E, NB, K, PD>((const E*)D.P, D.Jmax, (E*)D.Qs, D.rows_pad, D.n, local % D.G,
                         m, t - (D.M - 1 - m), D.S);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-template <int NB, int K>
+template <typename E, int NB, int K>
 size_t split_pbytes(int64_t M, int64_t Jmax) {
   // + 32 values: the extra-segment loads of the last record read past it
-  return align256(((size_t)M * (size_t)Jmax * K * SplitGeom<NB, K>::RS + 32) * sizeof(double));
+  return align256(((size_t)M * (size_t)Jmax * K * SplitGeom<NB, K>::RS + 32) * sizeof(E));
 }
 
-template <int NB, int K, int OCC, int PD>
+template <typename E, int NB, int K, int OCC, int PD>
 hipError_t launch_split(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
                         int64_t nev, TileOpts opt, hipStream_t st, int num_cu) {
   using Gm = SplitGeom<NB, K>;
-  static const int64_t slots = wave_slots(k_split<NB, K, OCC, PD>, num_cu);
+  static const int64_t slots = wave_slots(k_split<E, NB, K, OCC, PD>, num_cu);
   const int64_t S = opt.steps > 0 ? opt.steps : choose_steps(n, nev, NB, K, slots, Gm::SW);
   const DiagPlan pl(n, nev, NB, K, S, Gm::SW);
   const int64_t Jmax = (n - 1 + NB - 1) / NB;
   if (pl.G * pl.M >= INT32_MAX || pl.M * Jmax >= INT32_MAX || n + NB + K >= INT32_MAX)
     return hipErrorInvalidValue;
-  const size_t pbytes = split_pbytes<NB, K>(pl.M, Jmax);
+  const size_t pbytes = split_pbytes<E, NB, K>(pl.M, Jmax);
   char* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, pbytes + pl.template qbytes<double>(), st);
+  hipError_t err = hipMallocAsync((void**)&ws, pbytes + pl.template qbytes<E>(), st);
   if (err != hipSuccess) return err;
-  double* Pk = (double*)ws;
-  double* Qs = (double*)(ws + pbytes);
+  E* Pk = (E*)ws;
+  E* Qs = (E*)(ws + pbytes);
   const unsigned gt = (unsigned)((nev + 63) / 64);
-  hipLaunchKernelGGL((k_pack_split<NB, K>), dim3((unsigned)(pl.M * Jmax)), dim3(256), 0, st,
-                     (const double*)hh, (const double*)tau, n, Jmax, Pk);
-  hipLaunchKernelGGL(k_to_rows_sw<Gm::SW>, dim3((unsigned)(pl.rows_pad / 64), gt), dim3(256), 0,
-                     st, (const double*)Q, ldq, n, nev, Qs, pl.rows_pad, pl.G);
+  hipLaunchKernelGGL((k_pack_split<E, NB, K>), dim3((unsigned)(pl.M * Jmax)), dim3(256), 0, st,
+                     (const E*)hh, (const E*)tau, n, Jmax, Pk);
+  hipLaunchKernelGGL((k_to_rows_sw<E, Gm::SW>), dim3((unsigned)(pl.rows_pad / 64), gt), dim3(256), 0,
+                     st, (const E*)Q, ldq, n, nev, Qs, pl.rows_pad, pl.G);
   const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(opt.streams, pl.G));
   ProfScope prof(st, K, S, ns);
   {
@@ -376,8 +449,8 @@ hipError_t launch_split(const void* hh, const void* tau, void* Q, int64_t ldq, i
       for (int i = 0; i < ns; ++i) {
         const int64_t c_lo = pl.G * i / ns, gs = pl.G * (i + 1) / ns - c_lo;
         prof.before(fork.stream(i));
-        hipLaunchKernelGGL((k_split<NB, K, OCC, PD>), dim3((unsigned)(cnt * gs)), dim3(64), 0,
-                           fork.stream(i), (const double*)Pk, Jmax, Qs, pl.rows_pad, n, (int)c_lo,
+        hipLaunchKernelGGL((k_split<E, NB, K, OCC, PD>), dim3((unsigned)(cnt * gs)), dim3(64), 0,
+                           fork.stream(i), (const E*)Pk, Jmax, Qs, pl.rows_pad, n, (int)c_lo,
                            (int)gs, (int)pl.M, (int)t, (int)m0, (int)S, opt.xcd);
         prof.after(fork.stream(i));
       }
@@ -389,8 +462,8 @@ hipError_t launch_split(const void* hh, const void* tau, void* Q, int64_t ldq, i
     (void)hipFreeAsync(ws, st);
     return err;
   }
-  hipLaunchKernelGGL(k_from_rows_sw<Gm::SW>, dim3((unsigned)((n + 63) / 64), gt), dim3(256), 0,
-                     st, (const double*)Qs, pl.rows_pad, (double*)Q, ldq, n, nev, pl.G);
+  hipLaunchKernelGGL((k_from_rows_sw<E, Gm::SW>), dim3((unsigned)((n + 63) / 64), gt), dim3(256), 0,
+                     st, (const E*)Qs, pl.rows_pad, (E*)Q, ldq, n, nev, pl.G);
   err = hipGetLastError();
   const hipError_t e2 = hipFreeAsync(ws, st);
   return err != hipSuccess ? err : e2;
@@ -398,12 +471,12 @@ hipError_t launch_split(const void* hh, const void* tau, void* Q, int64_t ldq, i
 
 // Batched: problems idx[0..cnt) of probs (real fp64, semi-bandwidth NB,
 // validated by the caller); all problems' diagonal schedules run side by side.
-template <int NB, int K, int OCC, int PD>
+template <typename E, int NB, int K, int OCC, int PD>
 hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
                                 TileOpts opt, hipStream_t st, int num_cu) {
   using Gm = SplitGeom<NB, K>;
   const int64_t S = opt.steps;
-  static const int64_t slots = wave_slots(k_split_b<NB, K, OCC, PD>, num_cu);
+  static const int64_t slots = wave_slots(k_split_b<E, NB, K, OCC, PD>, num_cu);
   std::vector<ProblemDesc> d;
   std::vector<DiagPlan> plans;
   int64_t total_cols = 0;
@@ -445,9 +518,9 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
     otiles += (size_t)((pl.n + 63) / 64 * d[i].GT);
     ptiles += (size_t)(pl.M * Jmax);
     pat[i] = off;
-    off += split_pbytes<NB, K>(pl.M, Jmax);
+    off += split_pbytes<E, NB, K>(pl.M, Jmax);
     qat[i] = off;
-    off += pl.template qbytes<double>();
+    off += pl.template qbytes<E>();
     T = std::max(T, pl.T);
   }
   std::vector<DiagEntry> ent;
@@ -491,41 +564,46 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
   const ProblemDesc* dd = (const ProblemDesc*)ws;
   const DiagEntry* de = (const DiagEntry*)(ws + dbytes);
   const int count = (int)d.size();
-  hipLaunchKernelGGL((k_pack_split_b<NB, K>), dim3((unsigned)ptiles), dim3(256), 0, st, dd, count);
-  hipLaunchKernelGGL(k_to_rows_sw_b<Gm::SW>, dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
+  hipLaunchKernelGGL((k_pack_split_b<E, NB, K>), dim3((unsigned)ptiles), dim3(256), 0, st, dd, count);
+  hipLaunchKernelGGL((k_to_rows_sw_b<E, Gm::SW>), dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
   ProfScope prof(st, K, S);
   for (int64_t t = 0; t < T; ++t) {
     const int64_t ne = eoff[(size_t)t + 1] - eoff[(size_t)t];
     if (ne == 0) continue;
     prof.before(st);
-    hipLaunchKernelGGL((k_split_b<NB, K, OCC, PD>), dim3((unsigned)etiles[(size_t)t]), dim3(64), 0,
+    hipLaunchKernelGGL((k_split_b<E, NB, K, OCC, PD>), dim3((unsigned)etiles[(size_t)t]), dim3(64), 0,
                        st, dd, de + eoff[(size_t)t], (int)ne, (int)t, opt.xcd);
     prof.after(st);
   }
   prof.end();
-  hipLaunchKernelGGL(k_from_rows_sw_b<Gm::SW>, dim3((unsigned)otiles), dim3(256), 0, st, dd,
+  hipLaunchKernelGGL((k_from_rows_sw_b<E, Gm::SW>), dim3((unsigned)otiles), dim3(256), 0, st, dd,
                      count);
   err = hipGetLastError();
   const hipError_t e2 = hipFreeAsync(ws, st);
   return err != hipSuccess ? err : e2;
 }
 
-template <int NB, int K>
+template <typename E, int NB, int K>
 size_t split_workspace(int64_t n, int64_t nev) {
   const DiagPlan pl(n, nev, NB, K, 1, SplitGeom<NB, K>::SW);
-  return split_pbytes<NB, K>(pl.M, (n - 1 + NB - 1) / NB) + pl.template qbytes<double>();
+  return split_pbytes<E, NB, K>(pl.M, (n - 1 + NB - 1) / NB) + pl.template qbytes<E>();
 }
 
-#define EHH_SPLIT(NB, K, OCC, PD)                                               \
-  {ELPA_PATH_SPLIT, 0, NB, K, OCC, &launch_split<NB, K, OCC, PD>,                 \
-   &launch_split_batched<NB, K, OCC, PD>, &split_workspace<NB, K>}
+#define EHH_SPLIT(E, DT, NB, K, OCC, PD)                                               \
+  {ELPA_PATH_SPLIT, DT, NB, K, OCC, &launch_split<E, NB, K, OCC, PD>,                    \
+   &launch_split_batched<E, NB, K, OCC, PD>, &split_workspace<E, NB, K>}
 
 const StripeEntry* split_table(int* size) {
   static const StripeEntry table[] = {
-      EHH_SPLIT(32, 32, 2, 2), EHH_SPLIT(32, 64, 2, 2), EHH_SPLIT(32, 96, 2, 2),
+      EHH_SPLIT(double, 0, 32, 32, 2, 2), EHH_SPLIT(double, 0, 32, 64, 2, 2),
+      EHH_SPLIT(double, 0, 32, 96, 2, 2),
       // k = 48 and 64 fit three waves per SIMD, k = 80 two (with the values of three
       // reflectors in flight)
-      EHH_SPLIT(64, 48, 2, 4), EHH_SPLIT(64, 64, 2, 2), EHH_SPLIT(64, 80, 2, 3),
+      EHH_SPLIT(double, 0, 64, 48, 2, 4), EHH_SPLIT(double, 0, 64, 64, 2, 2),
+      EHH_SPLIT(double, 0, 64, 80, 2, 3),
+      // complex: each window register holds two fp64 values
+      EHH_SPLIT(z64, 2, 64, 16, 2, 2), EHH_SPLIT(z64, 2, 64, 24, 2, 1),
+      EHH_SPLIT(z64, 2, 32, 32, 2, 2), EHH_SPLIT(z64, 2, 32, 48, 2, 1),
   };
   *size = (int)(sizeof(table) / sizeof(table[0]));
   return table;

@@ -115,7 +115,9 @@ def test_plan_support_table():
         assert P.plan_supported(nbw, P.R64, P.PATH_SPLIT, k), (nbw, k)
     assert P.plan_supported(64, P.R64, P.PATH_SPLIT)          # library default k
     assert not P.plan_supported(64, P.R32, P.PATH_SPLIT, 64)
-    assert not P.plan_supported(64, P.C64, P.PATH_SPLIT)
+    assert P.plan_supported(64, P.C64, P.PATH_SPLIT)           # complex: k = 24 default
+    assert P.plan_supported(64, P.C64, P.PATH_SPLIT, 16)
+    assert not P.plan_supported(64, P.C64, P.PATH_SPLIT, 80)
     assert not P.plan_supported(64, P.R64, P.PATH_SPLIT, 63)
     assert not P.plan_supported(16, P.R64, P.PATH_SPLIT)
     assert not P.plan_supported(64, P.R64, 5)                # no such path

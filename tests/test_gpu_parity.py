@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
 KS = [1, 2, 4, 6, 8, 16, 24, 32, 40, 48, 64]
-SPLIT_KS = [32, 48, 64, 80, 96]
+SPLIT_KS = [16, 24, 32, 48, 64, 80, 96]
 WY_KS = [32, 48, 64, 96]
 
 
@@ -220,6 +220,25 @@ def test_wy_path_tilings(torch_dev, dt, nbw, k):
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("nbw,k", [(64, 16), (64, 24), (32, 32), (32, 48)])
+def test_split_complex_tilings(torch_dev, nbw, k):
+    """Two-lane kernel on complex values: tiles of 1, 3 and 16 chase steps and
+    two stripe groups give bitwise equal results that match the oracle."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nev = 900, 77
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "c64", 131 + k)
+    ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
+    outs = []
+    for steps, ns in ((1, 1), (3, 1), (16, 2)):
+        print(f"split c64 n={n} nbw={nbw} k={k} steps={steps} streams={ns}", flush=True)
+        got = run_gpu(torch, dev, hh, tau, Z, nbw, "c64", P.PATH_SPLIT, k, steps=steps,
+                      streams=ns)
+        assert checks.max_rel_err(got, ref) <= TOL["c64"], steps
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
 def test_profile_reports_main_kernel_sequence(torch_dev):
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
@@ -293,6 +312,7 @@ FULL = [
     (20000, 64, 2000, "r64", (2, 32)),   # one-lane stripe kernel at full size
     (20000, 64, 2000, "r64", (4, 64)),   # compact-WY MFMA path
     (20000, 64, 2000, "r32", (4, 64)),
+    (20000, 64, 2000, "c64", (2, 4)),    # one-lane stripe kernel, complex
     (20000, 64, 2000, "r32", None), (20000, 64, 2000, "c64", None),
 ]
 
