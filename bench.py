@@ -37,7 +37,7 @@ def parse():
     ap.add_argument("--nev", type=int, default=20000)
     ap.add_argument("--dtype", default="r64", choices=["r64", "r32", "c64"])
     ap.add_argument("--path", type=int, default=0,
-                    help="0 auto, 1 reference, 2 one-lane stripe, 3 two-lane stripe")
+                    help="0 auto, 1 reference, 2 one-lane stripe, 3 two-lane stripe, 4 compact WY")
     ap.add_argument("--k", type=int, default=0, help="sweeps fused per pass (0 = auto)")
     ap.add_argument("--tile-steps", type=int, default=0,
                     help="chase steps per tile of the launch schedule (0 = auto)")
@@ -48,6 +48,7 @@ def parse():
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served SCF stream leg")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched workload leg")
     ap.add_argument("--served-rates", default="120,250",
                     help="Poisson arrival rates of the served stream (requests / s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -109,6 +110,63 @@ def served_stream(args):
     return {"workload": f"{nseq} sequences x {steps} solves, n ~ U{{1000..6000}}, nbw 64, "
                         f"nev = n, Poisson arrivals, 25% fp32; slots 3, max batch 32",
             "runs": runs}
+
+
+def batched_workload():
+    """The batched workload: 256 real fp64 problems, n_i ~ U{200..2000}
+    (seed 401), nbw 32, nev = n_i, all back-transforms in one batched call
+    (inputs drawn on the device).  Timed with the library's default plan, then
+    with the uniform plan the batch tuner picks (kernel family, k, tile height,
+    stripe groups) over the whole batch; for comparison, with plans tuned one
+    problem at a time per size class of n, and one call per problem."""
+    import torch
+    import workload as W
+    import paper_1811_01277_amd as P
+    dev = torch.device("cuda:0")
+    sizes = [int(x) for x in W.batched_sizes(256, 200, 2000, seed=401)]
+    g = torch.Generator(device=dev)
+    g.manual_seed(401000)
+    probs = []
+    for n in sizes:
+        hh, tau = W.device_reflectors(torch, n, 32, dev, g)
+        probs.append((W.device_block(torch, n, n, dev, g), hh, tau, 32))
+    flops = sum(2 * n * (n - 1) * n for n in sizes)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    P.tuner_clear()
+    t_default = timed(lambda: P.hh_trafo_batched(probs))
+    t_single = timed(lambda: [P.hh_trafo(q, h, t, nbw) for (q, h, t, nbw) in probs], reps=1)
+    # one uniform plan timed over the whole batch
+    t0 = time.perf_counter()
+    plan = P.tune_batched(probs, level=1)
+    tune_s = time.perf_counter() - t0
+    t_tuned = timed(lambda: P.hh_trafo_batched(probs, **plan))
+    # for contrast: plans tuned one problem at a time, per size class of n
+    classes = {}
+    for i, n in enumerate(sizes):
+        classes.setdefault(int(np.floor(4 * np.log2(n) + 1e-9)), i)
+    for i in classes.values():
+        q, h, t, nbw = probs[i]
+        P.tune(q, h, t, nbw, level=1)
+    t_class = timed(lambda: P.hh_trafo_batched(probs))
+    P.tuner_clear()
+    return {"workload": "256 real fp64 problems, n ~ U{200..2000}, nbw 32, nev = n, one call",
+            "gflops_default": round(flops / t_default / 1e6, 1),
+            "ms_default": round(t_default, 3),
+            "gflops_tuned": round(flops / t_tuned / 1e6, 1), "ms_tuned": round(t_tuned, 3),
+            "tuned_plan": plan, "tuning_s": round(tune_s, 1),
+            "gflops_per_class_single_call_plans": round(flops / t_class / 1e6, 1),
+            "gflops_one_call_per_problem": round(flops / t_single / 1e6, 1)}
 
 
 def recorded_traffic(workload):
@@ -276,6 +334,9 @@ def main():
     }
     del q, h, t
     torch.cuda.empty_cache()
+    if not args.no_batched:
+        out["batched_workload"] = batched_workload()
+        torch.cuda.empty_cache()
     if not args.no_served:
         out["served_stream"] = served_stream(args)
         torch.cuda.empty_cache()

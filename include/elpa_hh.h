@@ -221,9 +221,10 @@ int elpa_hh_profile_last(elpa_hh_profile *out);
  * (dtype, nbw, size class of n, size class of nev); size classes are quarter
  * octaves (floor(4 log2 x)), so sizes within about 19 % share a plan.  Calls
  * without an explicit plan (NULL, or a plan whose fields are all 0) use the
- * cached plan of their class when there is one; batched calls do so per
- * problem (problems whose plans pick different kernels run as separate launch
- * sequences, in order).
+ * cached plan of their class when there is one, and so do the workspace
+ * queries; batched calls do so per problem (problems whose plans pick
+ * different kernels run as separate launch sequences, in order, which can be
+ * slower for a batch than one uniform plan: see elpa_hh_tune_batched).
  *
  * elpa_hh_tune times candidate plans on a scratch copy of Q (Q itself is not
  * modified; the call allocates ldq*nev elements and waits for `stream`) and
@@ -243,6 +244,20 @@ int elpa_hh_profile_last(elpa_hh_profile *out);
 int elpa_hh_tune(int64_t n, int64_t nev, int64_t nbw, const void *hh, const void *tau,
                  const void *Q, int64_t ldq, int32_t dtype, void *stream, int32_t level,
                  elpa_hh_plan *best);
+
+/*
+ * Batch tuner: times uniform plans (one plan for every problem, among those
+ * that every problem of the batch can run in a batched call) on scratch
+ * copies of the problems' Q (the Q buffers are not modified; the call
+ * allocates the sum of the spans ldq*(nev-1)+n and waits for `stream`) and
+ * returns the fastest in *best, to be passed to elpa_hh_trafo_batched.  The
+ * result is not cached: a batch's best plan depends on the whole mix of sizes
+ * sharing the device, not on one problem's size class.  level as for
+ * elpa_hh_tune.  Errors: ELPA_ERR_ARG for count <= 0, a NULL probs or level
+ * out of range, otherwise those of elpa_hh_trafo_batched.
+ */
+int elpa_hh_tune_batched(const elpa_hh_problem *probs, int64_t count, void *stream,
+                         int32_t level, elpa_hh_plan *best);
 int elpa_hh_tuner_set(int32_t dtype, int64_t nbw, int64_t n, int64_t nev,
                       const elpa_hh_plan *plan);
 int elpa_hh_tuner_get(int32_t dtype, int64_t nbw, int64_t n, int64_t nev, elpa_hh_plan *out);

@@ -13,6 +13,6 @@ from .binding import (  # noqa: F401
     R32, R64, ElpaError, hh_trafo,
     hh_trafo_batched, hh_trafo_ptr, library, library_path, num_reflectors, plan_supported,
     profile_enable, profile_last, slot_offset, strerror, version, workspace_bytes,
-    workspace_bytes_batched, tune, tuner_clear, tuner_get, tuner_load, tuner_save, tuner_set,
+    workspace_bytes_batched, tune, tune_batched, tuner_clear, tuner_get, tuner_load, tuner_save, tuner_set,
     tuner_size,
 )

@@ -67,6 +67,8 @@ def library():
         L.elpa_hh_workspace_bytes_batched.restype = i64
         L.elpa_hh_tune.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, i32, C.POINTER(_Plan)]
         L.elpa_hh_tune.restype = C.c_int
+        L.elpa_hh_tune_batched.argtypes = [C.POINTER(_Problem), i64, p, i32, C.POINTER(_Plan)]
+        L.elpa_hh_tune_batched.restype = C.c_int
         L.elpa_hh_tuner_set.argtypes = [i32, i64, i64, i64, C.POINTER(_Plan)]
         L.elpa_hh_tuner_set.restype = C.c_int
         L.elpa_hh_tuner_get.argtypes = [i32, i64, i64, i64, C.POINTER(_Plan)]
@@ -271,13 +273,8 @@ def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0, order=0, str
     return q
 
 
-def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, streams=0):
-    """Batched Q <- H ... H Q over a list of (q, hh, tau, nbw) tensor tuples.
-
-    Each q is a column-major (n, nev) device tensor as in hh_trafo; problems
-    may differ in n, nev and dtype.  One persistent launch per (dtype, nbw)
-    group on one stream.
-    """
+def _marshal_batch(problems, stream):
+    """C problem array and raw stream of a list of (q, hh, tau, nbw) tuples."""
     import torch
     arr = (_Problem * max(1, len(problems)))()
     dev = None
@@ -300,8 +297,31 @@ def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, st
         st = stream
     else:
         st = stream.cuda_stream
+    return arr, st
+
+
+def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, streams=0):
+    """Batched Q <- H ... H Q over a list of (q, hh, tau, nbw) tensor tuples.
+
+    Each q is a column-major (n, nev) device tensor as in hh_trafo; problems
+    may differ in n, nev and dtype.  One persistent launch per (dtype, nbw)
+    group on one stream.
+    """
+    arr, st = _marshal_batch(problems, stream)
     pl = _plan(path, k, steps, order, streams)
     rc = int(library().elpa_hh_trafo_batched(arr, len(problems), C.c_void_p(st),
                                               C.byref(pl) if pl is not None else None))
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
+    return problems
+
+
+def tune_batched(problems, level=0, stream=None):
+    """Time uniform plans over the whole batch (the Q tensors are not
+    modified) and return the fastest as a dict, to pass to hh_trafo_batched
+    as keyword arguments.  Not cached."""
+    arr, st = _marshal_batch(problems, stream)
+    out = _Plan()
+    _check(library().elpa_hh_tune_batched(arr, len(problems), C.c_void_p(st), level,
+                                           C.byref(out)))
+    return _plan_dict(out)

@@ -295,6 +295,8 @@ int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void* hh, const voi
 int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dtype,
                                 const elpa_hh_plan* plan) {
   if (n < 0 || nev < 0 || nbw < 1 || elem_size(dtype) == 0) return -1;
+  elpa_hh_plan tuned{};
+  plan = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0, rc = 0;
   const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc);
   if (rc != ELPA_OK) return -1;
@@ -309,8 +311,10 @@ int64_t elpa_hh_workspace_bytes_batched(const elpa_hh_problem* probs, int64_t co
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
     if (p.n < 0 || p.nev < 0 || p.nbw < 1 || elem_size(p.dtype) == 0) return -1;
+    elpa_hh_plan tuned{};
+    const elpa_hh_plan* pp = effective_plan(p.dtype, p.nbw, p.n, p.nev, plan, &tuned);
     int path = 0, rc = 0;
-    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, plan, &path, &rc, true);
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, pp, &path, &rc, true);
     if (rc != ELPA_OK) return -1;
     if (p.n <= 1 || p.nev == 0 || !se) continue;
     total += (int64_t)se->workspace(p.n, p.nev);

@@ -15,6 +15,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <set>
 #include <tuple>
 #include <vector>
 
@@ -216,6 +217,91 @@ int elpa_hh_tune(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void
     std::lock_guard<std::mutex> g(c.mu);
     c.plans[ehh::key_of(dtype, nbw, n, nev)] = win;
   }
+  if (best) *best = win;
+  return ELPA_OK;
+}
+
+int elpa_hh_tune_batched(const elpa_hh_problem* probs, int64_t count, void* stream, int32_t level,
+                         elpa_hh_plan* best) {
+  if (level < 0 || level > 2 || count <= 0 || !probs) return ELPA_ERR_ARG;
+  // scratch copies of every Q (the span ldq*(nev-1)+n of each), 256-aligned
+  std::vector<elpa_hh_problem> work(probs, probs + count);
+  std::vector<size_t> off(count, 0), len(count, 0);
+  size_t total = 0;
+  for (int64_t i = 0; i < count; ++i) {
+    const elpa_hh_problem& p = probs[i];
+    const int64_t es = p.dtype == ELPA_C64 ? 16 : p.dtype == ELPA_R64 ? 8 : p.dtype == ELPA_R32 ? 4 : 0;
+    if (es == 0) return ELPA_ERR_DTYPE;
+    if (p.n < 0 || p.nev < 0 || p.nbw < 1) return ELPA_ERR_ARG;
+    if (p.n <= 1 || p.nev == 0) continue;
+    if (p.ldq < p.n || !p.Q) return ELPA_ERR_ARG;
+    if (p.nev > 1 && p.ldq > (INT64_MAX / es - p.n) / (p.nev - 1)) return ELPA_ERR_ARG;
+    len[i] = ((size_t)p.ldq * (size_t)(p.nev - 1) + (size_t)p.n) * (size_t)es;
+    off[i] = total;
+    total += (len[i] + 255) / 256 * 256;
+  }
+  // candidates: uniform plans that every problem of the batch can run
+  std::vector<elpa_hh_plan> cand;
+  const int steps_list[] = {0, 2, 4, 8, 16};
+  const int nsteps = level == 2 ? 5 : 1;
+  for (int fam : {ELPA_PATH_SPLIT, ELPA_PATH_WY, ELPA_PATH_STRIPE}) {
+    std::set<int> ks;
+    if (level == 0) {
+      ks.insert(0);
+    } else {
+      int cnt = 0;
+      const ehh::StripeEntry* tab = fam == ELPA_PATH_SPLIT ? ehh::split_table(&cnt)
+                                    : fam == ELPA_PATH_WY  ? ehh::wy_table(&cnt)
+                                                           : ehh::stripe_table(&cnt);
+      for (int i = 0; i < cnt; ++i) ks.insert(tab[i].k);
+    }
+    for (int k : ks)
+      for (int si = 0; si < nsteps; ++si)
+        for (int streams : {1, 2}) {
+          const elpa_hh_plan p{fam, k, steps_list[si], 0, streams, 0};
+          if (elpa_hh_workspace_bytes_batched(probs, count, &p) >= 0) cand.push_back(p);
+        }
+  }
+  if (cand.empty()) cand.push_back(elpa_hh_plan{ELPA_PATH_REF, 0, 0, 0, 0, 0});
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  char* scratch = nullptr;
+  if (total > 0 && hipMallocAsync((void**)&scratch, total, st) != hipSuccess) return ELPA_ERR_NOMEM;
+  bool ok = true;
+  for (int64_t i = 0; ok && i < count; ++i) {
+    if (len[i] == 0) continue;
+    work[i].Q = scratch + off[i];
+    ok = hipMemcpyAsync(work[i].Q, probs[i].Q, len[i], hipMemcpyDeviceToDevice, st) == hipSuccess;
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  ok = ok && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess;
+  float best_ms = -1.f;
+  elpa_hh_plan win{};
+  const int reps = 2;
+  int rc = ELPA_OK;
+  for (size_t c = 0; ok && c < cand.size(); ++c) {
+    const elpa_hh_plan& p = cand[c];
+    rc = elpa_hh_trafo_batched(work.data(), count, stream, &p);  // warm-up and checks
+    if (rc != ELPA_OK) {
+      ok = false;
+      break;
+    }
+    ok = hipEventRecord(a, st) == hipSuccess;
+    for (int r = 0; ok && r < reps; ++r)
+      ok = elpa_hh_trafo_batched(work.data(), count, stream, &p) == ELPA_OK;
+    ok = ok && hipEventRecord(b, st) == hipSuccess && hipEventSynchronize(b) == hipSuccess;
+    float ms = 0.f;
+    ok = ok && hipEventElapsedTime(&ms, a, b) == hipSuccess;
+    if (ok && (best_ms < 0.f || ms < best_ms)) {
+      best_ms = ms;
+      win = p;
+    }
+  }
+  if (scratch) (void)hipFreeAsync(scratch, st);
+  (void)hipStreamSynchronize(st);
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  if (rc != ELPA_OK) return rc;
+  if (!ok || best_ms < 0.f) return ELPA_ERR_DEVICE;
   if (best) *best = win;
   return ELPA_OK;
 }

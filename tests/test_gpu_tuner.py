@@ -1,7 +1,8 @@
 """GPU tests of the plan tuner: elpa_hh_tune leaves Q untouched and caches a
 runnable plan; calls without a plan then run it; a batch whose problems have
 plans with different kernels runs them as separate launch sequences with the
-same results as single calls."""
+same results as single calls; the batch tuner leaves every Q untouched and
+returns a uniform plan whose batched run equals single calls under it."""
 import numpy as np
 import pytest
 
@@ -90,3 +91,34 @@ def test_batch_with_tuned_plans_of_different_kernels(torch_dev):
         assert torch.equal(q, s)
         ref = bt.bt_tridiag_to_band(hh, tau, Z, n, 64)
         assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12
+
+
+def test_tune_batched_keeps_q_and_plan_runs(torch_dev):
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    sizes = [200, 333, 470, 610, 257, 700]
+    probs, host, before = [], [], []
+    for i, n in enumerate(sizes):
+        q, h, t, hst = make(torch, dev, n, 32, n, 1300 + i)
+        probs.append((q, h, t, 32))
+        host.append(hst)
+        before.append(q.clone())
+    print("tune batched level 1", flush=True)
+    plan = P.tune_batched(probs, level=1)
+    torch.cuda.synchronize()
+    print("tuned batch plan", plan, flush=True)
+    assert P.tuner_size() == 0, "batch plans are not cached"
+    for q, b in zip(probs, before):
+        assert torch.equal(q[0], b), "tuning modified Q"
+    assert plan["path"] in (P.PATH_SPLIT, P.PATH_WY, P.PATH_STRIPE)
+    singles = []
+    for (q, h, t, nbw) in probs:
+        qq = q.clone()
+        P.hh_trafo(qq, h, t, nbw, **plan)
+        singles.append(qq)
+    P.hh_trafo_batched(probs, **plan)
+    torch.cuda.synchronize()
+    for (q, _, _, _), s, (hh, tau, Z), n in zip(probs, singles, host, sizes):
+        assert torch.equal(q, s), n
+        ref = bt.bt_tridiag_to_band(hh, tau, Z, n, 32)
+        assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12, n

@@ -76,3 +76,32 @@ def test_load_refuses_bad_files_whole(tmp_path, body):
     assert P.tuner_size() == 1                           # cache unchanged
     with pytest.raises(P.ElpaError):
         P.tuner_load(os.path.join(str(tmp_path), "missing.txt"))
+
+
+def test_workspace_queries_follow_tuned_plan():
+    # a call without a plan runs the tuned plan, so its workspace is that plan's
+    n, nev = 20000, 20000
+    wy = P.workspace_bytes(n, nev, 64, P.R64, path=P.PATH_WY, k=32)
+    assert P.workspace_bytes(n, nev, 64, P.R64) != wy
+    P.tuner_set(P.R64, 64, n, nev, path=P.PATH_WY, k=32)
+    assert P.workspace_bytes(n, nev, 64, P.R64) == wy
+    one = [(n, nev, 64, P.R64)]
+    assert (P.workspace_bytes_batched(one) ==
+            P.workspace_bytes_batched(one, path=P.PATH_WY, k=32))
+
+
+def test_tune_batched_argument_errors():
+    # rejected before anything touches a device
+    with pytest.raises(P.ElpaError) as e:
+        P.tune_batched([], level=0, stream=0)
+    assert e.value.code == -1
+    import ctypes as C
+    from paper_1811_01277_amd import binding as B
+    arr = (B._Problem * 1)()
+    arr[0] = B._Problem(100, 10, 32, 100, None, None, None, P.R64, 0)
+    out = B._Plan()
+    assert B.library().elpa_hh_tune_batched(arr, 1, None, 3, C.byref(out)) == -1   # level
+    arr[0] = B._Problem(100, 10, 32, 99, None, None, None, P.R64, 0)
+    assert B.library().elpa_hh_tune_batched(arr, 1, None, 0, C.byref(out)) == -1   # ldq < n
+    arr[0] = B._Problem(100, 10, 32, 100, None, None, None, 7, 0)
+    assert B.library().elpa_hh_tune_batched(arr, 1, None, 0, C.byref(out)) == -2   # dtype
