@@ -73,10 +73,8 @@ __device__ __forceinline__ void dpp_upd2(double& x0, double& x1, double V0, doub
 // Split-window blocks (two lanes per column, rows interleaved by parity).
 // A reflector's values for one lane half arrive as 16-value segments held in
 // VGPR pairs (lane 16r+i holds segment value i); each block below covers
-// broadcast lanes l0..l7 of one or two segments, so a reflector takes two
-// blocks per pass and one s_nop per 8 or 16 FMAs.  The _X forms add the
-// extra term of an odd window offset: segment 2's lane-0 value against one
-// more window row.
+// broadcast lanes l0..l7 of one or two segments.  The extra term of an odd
+// window offset is segment 2's lane-0 value against one more window row.
 // ---------------------------------------------------------------------------
 #define EHH_F(D, S, X, L) \
   "v_fmac_f64_dpp %" #D ", %" #S ", %" #X " row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n"
@@ -89,91 +87,134 @@ __device__ __forceinline__ void dpp_upd2(double& x0, double& x1, double V0, doub
   "+v"(p[0]), "+v"(p[1]), "+v"(p[2]), "+v"(p[3]), "+v"(p[4]), "+v"(p[5]), "+v"(p[6]), \
       "+v"(p[7])
 
-// one segment: a0/a1 += bcast(V0, l) * x  (%0 a0, %1 a1, %2 V0, %3..%10 x)
-#define EHH_SDOT1(l0, l1, l2, l3, l4, l5, l6, l7)                                      \
-  EHH_F(0, 2, 3, l0) EHH_F(1, 2, 4, l1) EHH_F(0, 2, 5, l2) EHH_F(1, 2, 6, l3)          \
-  EHH_F(0, 2, 7, l4) EHH_F(1, 2, 8, l5) EHH_F(0, 2, 9, l6) EHH_F(1, 2, 10, l7)
-// one segment: x += bcast(V, l) * nw  (%0..%7 x)
-#define EHH_SUPD1(V, NW, l0, l1, l2, l3, l4, l5, l6, l7)                                \
-  EHH_F(0, V, NW, l0) EHH_F(1, V, NW, l1) EHH_F(2, V, NW, l2) EHH_F(3, V, NW, l3)      \
-  EHH_F(4, V, NW, l4) EHH_F(5, V, NW, l5) EHH_F(6, V, NW, l6) EHH_F(7, V, NW, l7)
-// two segments: a0 += bcast(V0, l) * x, a1 += bcast(V1, l) * y
-// (%0 a0, %1 a1, %2 V0, %3 V1, %4..%11 x, %12..%19 y)
-#define EHH_SDOT2(l0, l1, l2, l3, l4, l5, l6, l7)                                      \
-  EHH_F(0, 2, 4, l0) EHH_F(1, 3, 12, l0) EHH_F(0, 2, 5, l1) EHH_F(1, 3, 13, l1)        \
-  EHH_F(0, 2, 6, l2) EHH_F(1, 3, 14, l2) EHH_F(0, 2, 7, l3) EHH_F(1, 3, 15, l3)        \
-  EHH_F(0, 2, 8, l4) EHH_F(1, 3, 16, l4) EHH_F(0, 2, 9, l5) EHH_F(1, 3, 17, l5)        \
-  EHH_F(0, 2, 10, l6) EHH_F(1, 3, 18, l6) EHH_F(0, 2, 11, l7) EHH_F(1, 3, 19, l7)
-// two segments: x += bcast(V0, l) * nw, y += bcast(V1, l) * nw (%0..%7 x, %8..%15 y)
-#define EHH_SUPD2(V0, V1, NW, l0, l1, l2, l3, l4, l5, l6, l7)                                 \
-  EHH_F(0, V0, NW, l0) EHH_F(8, V1, NW, l0) EHH_F(1, V0, NW, l1) EHH_F(9, V1, NW, l1)        \
-  EHH_F(2, V0, NW, l2) EHH_F(10, V1, NW, l2) EHH_F(3, V0, NW, l3) EHH_F(11, V1, NW, l3)      \
-  EHH_F(4, V0, NW, l4) EHH_F(12, V1, NW, l4) EHH_F(5, V0, NW, l5) EHH_F(13, V1, NW, l5)      \
-  EHH_F(6, V0, NW, l6) EHH_F(14, V1, NW, l6) EHH_F(7, V0, NW, l7) EHH_F(15, V1, NW, l7)
+// ---------------------------------------------------------------------------
+// Reflector pairs.  Two consecutive reflectors A (applied first) and B of a
+// chase step start on the same window register in both lane halves, so their
+// dot products run in one pass over the registers (four accumulator chains)
+// and their updates in another: x += bcast(vA) nwA, then x += bcast(vB) nwB
+// on every register, A's terms before B's within a block.  Only A can carry
+// the extra term (it is the odd offset).
+// ---------------------------------------------------------------------------
+#define EHH_PDOT2(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_F(0, 4, 8, l0) EHH_F(2, 6, 8, l0) EHH_F(1, 5, 16, l0) EHH_F(3, 7, 16, l0) \
+  EHH_F(0, 4, 9, l1) EHH_F(2, 6, 9, l1) EHH_F(1, 5, 17, l1) EHH_F(3, 7, 17, l1) \
+  EHH_F(0, 4, 10, l2) EHH_F(2, 6, 10, l2) EHH_F(1, 5, 18, l2) EHH_F(3, 7, 18, l2) \
+  EHH_F(0, 4, 11, l3) EHH_F(2, 6, 11, l3) EHH_F(1, 5, 19, l3) EHH_F(3, 7, 19, l3) \
+  EHH_F(0, 4, 12, l4) EHH_F(2, 6, 12, l4) EHH_F(1, 5, 20, l4) EHH_F(3, 7, 20, l4) \
+  EHH_F(0, 4, 13, l5) EHH_F(2, 6, 13, l5) EHH_F(1, 5, 21, l5) EHH_F(3, 7, 21, l5) \
+  EHH_F(0, 4, 14, l6) EHH_F(2, 6, 14, l6) EHH_F(1, 5, 22, l6) EHH_F(3, 7, 22, l6) \
+  EHH_F(0, 4, 15, l7) EHH_F(2, 6, 15, l7) EHH_F(1, 5, 23, l7) EHH_F(3, 7, 23, l7)
+#define EHH_PUPD2(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_F(0, 16, 20, l0) EHH_F(8, 17, 20, l0) \
+  EHH_F(1, 16, 20, l1) EHH_F(9, 17, 20, l1) \
+  EHH_F(2, 16, 20, l2) EHH_F(10, 17, 20, l2) \
+  EHH_F(3, 16, 20, l3) EHH_F(11, 17, 20, l3) \
+  EHH_F(4, 16, 20, l4) EHH_F(12, 17, 20, l4) \
+  EHH_F(5, 16, 20, l5) EHH_F(13, 17, 20, l5) \
+  EHH_F(6, 16, 20, l6) EHH_F(14, 17, 20, l6) \
+  EHH_F(7, 16, 20, l7) EHH_F(15, 17, 20, l7) \
+  EHH_F(0, 18, 21, l0) EHH_F(8, 19, 21, l0) \
+  EHH_F(1, 18, 21, l1) EHH_F(9, 19, 21, l1) \
+  EHH_F(2, 18, 21, l2) EHH_F(10, 19, 21, l2) \
+  EHH_F(3, 18, 21, l3) EHH_F(11, 19, 21, l3) \
+  EHH_F(4, 18, 21, l4) EHH_F(12, 19, 21, l4) \
+  EHH_F(5, 18, 21, l5) EHH_F(13, 19, 21, l5) \
+  EHH_F(6, 18, 21, l6) EHH_F(14, 19, 21, l6) \
+  EHH_F(7, 18, 21, l7) EHH_F(15, 19, 21, l7)
+#define EHH_PUPD2X(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_F(0, 17, 21, l0) EHH_F(8, 18, 21, l0) \
+  EHH_F(1, 17, 21, l1) EHH_F(9, 18, 21, l1) \
+  EHH_F(2, 17, 21, l2) EHH_F(10, 18, 21, l2) \
+  EHH_F(3, 17, 21, l3) EHH_F(11, 18, 21, l3) \
+  EHH_F(4, 17, 21, l4) EHH_F(12, 18, 21, l4) \
+  EHH_F(5, 17, 21, l5) EHH_F(13, 18, 21, l5) \
+  EHH_F(6, 17, 21, l6) EHH_F(14, 18, 21, l6) \
+  EHH_F(7, 17, 21, l7) EHH_F(15, 18, 21, l7) \
+  EHH_F(0, 19, 22, l0) EHH_F(8, 20, 22, l0) \
+  EHH_F(1, 19, 22, l1) EHH_F(9, 20, 22, l1) \
+  EHH_F(2, 19, 22, l2) EHH_F(10, 20, 22, l2) \
+  EHH_F(3, 19, 22, l3) EHH_F(11, 20, 22, l3) \
+  EHH_F(4, 19, 22, l4) EHH_F(12, 20, 22, l4) \
+  EHH_F(5, 19, 22, l5) EHH_F(13, 20, 22, l5) \
+  EHH_F(6, 19, 22, l6) EHH_F(14, 20, 22, l6) \
+  EHH_F(7, 19, 22, l7) EHH_F(15, 20, 22, l7)
+#define EHH_PDOT1(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_F(0, 4, 6, l0) EHH_F(2, 5, 6, l0) \
+  EHH_F(1, 4, 7, l1) EHH_F(3, 5, 7, l1) \
+  EHH_F(0, 4, 8, l2) EHH_F(2, 5, 8, l2) \
+  EHH_F(1, 4, 9, l3) EHH_F(3, 5, 9, l3) \
+  EHH_F(0, 4, 10, l4) EHH_F(2, 5, 10, l4) \
+  EHH_F(1, 4, 11, l5) EHH_F(3, 5, 11, l5) \
+  EHH_F(0, 4, 12, l6) EHH_F(2, 5, 12, l6) \
+  EHH_F(1, 4, 13, l7) EHH_F(3, 5, 13, l7)
+#define EHH_PUPD1(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_F(0, 8, 10, l0) EHH_F(1, 8, 10, l1) EHH_F(2, 8, 10, l2) EHH_F(3, 8, 10, l3) \
+  EHH_F(4, 8, 10, l4) EHH_F(5, 8, 10, l5) EHH_F(6, 8, 10, l6) EHH_F(7, 8, 10, l7) \
+  EHH_F(0, 9, 11, l0) EHH_F(1, 9, 11, l1) EHH_F(2, 9, 11, l2) EHH_F(3, 9, 11, l3) \
+  EHH_F(4, 9, 11, l4) EHH_F(5, 9, 11, l5) EHH_F(6, 9, 11, l6) EHH_F(7, 9, 11, l7)
+#define EHH_PUPD1X(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_F(0, 9, 11, l0) EHH_F(1, 9, 11, l1) EHH_F(2, 9, 11, l2) EHH_F(3, 9, 11, l3) \
+  EHH_F(4, 9, 11, l4) EHH_F(5, 9, 11, l5) EHH_F(6, 9, 11, l6) EHH_F(7, 9, 11, l7) \
+  EHH_F(0, 10, 12, l0) EHH_F(1, 10, 12, l1) EHH_F(2, 10, 12, l2) EHH_F(3, 10, 12, l3) \
+  EHH_F(4, 10, 12, l4) EHH_F(5, 10, 12, l5) EHH_F(6, 10, 12, l6) EHH_F(7, 10, 12, l7)
 
-// dot, one segment, lanes 0..7 and lanes 8..15 (+ extra term when EX)
-__device__ __forceinline__ void sdot1_a(double& a0, double& a1, double V0, const double* x) {
-  asm volatile("s_nop 1\n" EHH_X(EHH_SDOT1, EHH_LA) : "+v"(a0), "+v"(a1) : "v"(V0), EHH_VX8(x));
-}
-template <bool EX>
-__device__ __forceinline__ void sdot1_b(double& a0, double& a1, double V0, double V2,
-                                        const double* x, const double* xe) {
-  if constexpr (EX)
-    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT1, EHH_LB) EHH_F(0, 11, 12, 0)
-                 : "+v"(a0), "+v"(a1)
-                 : "v"(V0), EHH_VX8(x), "v"(V2), "v"(xe[0]));
-  else
-    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT1, EHH_LB) : "+v"(a0), "+v"(a1) : "v"(V0), EHH_VX8(x));
-}
-// update, one segment
-__device__ __forceinline__ void supd1_a(double* x, double V0, double nw) {
-  asm volatile("s_nop 1\n" EHH_X(EHH_SUPD1, 8, 9, EHH_LA) : EHH_PX8(x) : "v"(V0), "v"(nw));
-}
-template <bool EX>
-__device__ __forceinline__ void supd1_b(double* x, double* xe, double V0, double V2, double nw) {
-  if constexpr (EX)
-    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD1, 9, 10, EHH_LB) EHH_F(8, 11, 10, 0)
-                 : EHH_PX8(x), "+v"(xe[0])
-                 : "v"(V0), "v"(nw), "v"(V2));
-  else
-    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD1, 8, 9, EHH_LB) : EHH_PX8(x) : "v"(V0), "v"(nw));
-}
-// dot, two segments
-__device__ __forceinline__ void sdot2_a(double& a0, double& a1, double V0, double V1,
+// pair dot, two segments: aA0/aA1 += vA . (x, y), aB0/aB1 += vB . (x, y)
+__device__ __forceinline__ void pdot2_a(double& aA0, double& aA1, double& aB0, double& aB1,
+                                        double VA0, double VA1, double VB0, double VB1,
                                         const double* x, const double* y) {
-  asm volatile("s_nop 1\n" EHH_X(EHH_SDOT2, EHH_LA)
-               : "+v"(a0), "+v"(a1)
-               : "v"(V0), "v"(V1), EHH_VX8(x), EHH_VX8(y));
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT2, EHH_LA)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), EHH_VX8(x), EHH_VX8(y));
 }
-template <bool EX>
-__device__ __forceinline__ void sdot2_b(double& a0, double& a1, double V0, double V1, double V2,
-                                        const double* x, const double* y, const double* xe) {
-  if constexpr (EX)
-    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT2, EHH_LB) EHH_F(0, 20, 21, 0)
-                 : "+v"(a0), "+v"(a1)
-                 : "v"(V0), "v"(V1), EHH_VX8(x), EHH_VX8(y), "v"(V2), "v"(xe[0]));
-  else
-    asm volatile("s_nop 1\n" EHH_X(EHH_SDOT2, EHH_LB)
-                 : "+v"(a0), "+v"(a1)
-                 : "v"(V0), "v"(V1), EHH_VX8(x), EHH_VX8(y));
+__device__ __forceinline__ void pdot2_b(double& aA0, double& aA1, double& aB0, double& aB1,
+                                        double VA0, double VA1, double VB0, double VB1,
+                                        double VA2, const double* x, const double* y,
+                                        const double* xe) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT2, EHH_LB) EHH_F(0, 24, 25, 0)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), EHH_VX8(x), EHH_VX8(y), "v"(VA2),
+                 "v"(xe[0]));
 }
-// update, two segments
-__device__ __forceinline__ void supd2_a(double* x, double* y, double V0, double V1, double nw) {
-  asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 16, 17, 18, EHH_LA)
+// pair update, two segments
+__device__ __forceinline__ void pupd2_a(double* x, double* y, double VA0, double VA1, double VB0,
+                                        double VB1, double nwA, double nwB) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PUPD2, EHH_LA)
                : EHH_PX8(x), EHH_PX8(y)
-               : "v"(V0), "v"(V1), "v"(nw));
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), "v"(nwA), "v"(nwB));
 }
-template <bool EX>
-__device__ __forceinline__ void supd2_b(double* x, double* y, double* xe, double V0, double V1,
-                                        double V2, double nw) {
-  if constexpr (EX)
-    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 17, 18, 19, EHH_LB) EHH_F(16, 20, 19, 0)
-                 : EHH_PX8(x), EHH_PX8(y), "+v"(xe[0])
-                 : "v"(V0), "v"(V1), "v"(nw), "v"(V2));
-  else
-    asm volatile("s_nop 1\n" EHH_X(EHH_SUPD2, 16, 17, 18, EHH_LB)
-                 : EHH_PX8(x), EHH_PX8(y)
-                 : "v"(V0), "v"(V1), "v"(nw));
+__device__ __forceinline__ void pupd2_b(double* x, double* y, double* xe, double VA0, double VA1,
+                                        double VB0, double VB1, double VA2, double nwA,
+                                        double nwB) {
+  asm volatile("s_nop 1\n" EHH_F(16, 23, 21, 0) EHH_X(EHH_PUPD2X, EHH_LB)
+               : EHH_PX8(x), EHH_PX8(y), "+v"(xe[0])
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), "v"(nwA), "v"(nwB), "v"(VA2));
+}
+// pair dot, one segment (accumulators alternate over the broadcast lanes)
+__device__ __forceinline__ void pdot1_a(double& aA0, double& aA1, double& aB0, double& aB1,
+                                        double VA0, double VB0, const double* x) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT1, EHH_LA)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VB0), EHH_VX8(x));
+}
+__device__ __forceinline__ void pdot1_b(double& aA0, double& aA1, double& aB0, double& aB1,
+                                        double VA0, double VB0, double VA2, const double* x,
+                                        const double* xe) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT1, EHH_LB) EHH_F(0, 14, 15, 0)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VB0), EHH_VX8(x), "v"(VA2), "v"(xe[0]));
+}
+// pair update, one segment
+__device__ __forceinline__ void pupd1_a(double* x, double VA0, double VB0, double nwA,
+                                        double nwB) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PUPD1, EHH_LA)
+               : EHH_PX8(x)
+               : "v"(VA0), "v"(VB0), "v"(nwA), "v"(nwB));
+}
+__device__ __forceinline__ void pupd1_b(double* x, double* xe, double VA0, double VB0, double VA2,
+                                        double nwA, double nwB) {
+  asm volatile("s_nop 1\n" EHH_F(8, 13, 11, 0) EHH_X(EHH_PUPD1X, EHH_LB)
+               : EHH_PX8(x), "+v"(xe[0])
+               : "v"(VA0), "v"(VB0), "v"(nwA), "v"(nwB), "v"(VA2));
 }
 
 // ---------------------------------------------------------------------------

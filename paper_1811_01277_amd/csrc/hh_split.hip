@@ -18,11 +18,16 @@
 //    (odd o: one more register, whose reflector value is zero in one half).
 //    The two halves' partial dot products are combined with a lane swap
 //    across the halves (v_permlane32_swap), identically in both halves.
+//    Real reflectors are applied in pairs (odd o, then o-1), which start on
+//    the same register: two dot products in one pass, a 2x2 triangular
+//    correction with the pair coupling, and one update pass, as the paper's
+//    CPU kernels fuse two or more reflectors (Sec. 3.1).
 // 2. Packed reflectors.  A pre-pass writes, for every (block m, step j,
 //    offset o), the reflector (m*K+o, j) in the order the lanes consume it:
 //    per lane half HN+1 values (index 2t+h-(o&1) of v, zero outside [0, L)),
-//    tau in the first half's spare slot, zeros for reflectors that do not
-//    exist.  The step body then needs no slot arithmetic and no branches.
+//    tau in the first half's spare slot, for real records of even o the pair
+//    coupling v(o).v(o+1) in the second half's, zeros for reflectors that do
+//    not exist.  The step body then needs no slot arithmetic and no branches.
 // 3. Stripes are 32 columns wide; a stripe row pair (rows 2p, 2p+1) is one
 //    contiguous 512-byte access of the wave.
 //
@@ -76,7 +81,34 @@ __device__ __forceinline__ void pack_group(const E* __restrict__ hh, const E* __
         if (i >= 0 && i < L) v = hh[slot * NB + i];
       }
     }
+    // real records: the second half's spare slot of an even offset holds the
+    // pair coupling, written below
+    if (std::is_same<E, double>::value && h == 1 && t == Gm::HS - 1 && (o & 1) == 0) continue;
     rec[e] = v;
+  }
+  if constexpr (std::is_same<E, double>::value) {
+    // pair coupling c = vB.vA of B = offset o (even) and A = o+1 (vA starts one
+    // window row below vB): one wave per pair, a fixed-order tree sum
+    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
+    for (int o = 2 * wave; o < K; o += 2 * ((int)blockDim.x >> 6)) {
+      const int64_t s = s0 + o, sa = s + 1;
+      const bool vb = (s <= n - 2) && (j < (n - 1 - s + NB - 1) / NB);
+      const bool va = o + 1 < K && (sa <= n - 2) && (j < (n - 1 - sa + NB - 1) / NB);
+      double prod = 0.0;
+      if (vb && va) {
+        const int64_t rb = s + 1 + j * NB;
+        const int64_t lb = (NB < n - rb) ? NB : n - rb;
+        const int64_t la = (NB < n - rb - 1) ? NB : n - rb - 1;
+        if (lane + 1 < lb && lane < la) {
+          const int64_t slot_b = ctot - csum(n - 1 - s, NB) + j;
+          const int64_t slot_a = ctot - csum(n - 1 - sa, NB) + j;
+          prod = hh[slot_b * NB + lane + 1] * hh[slot_a * NB + lane];
+        }
+      }
+#pragma unroll
+      for (int w = 32; w >= 1; w >>= 1) prod += __shfl_xor(prod, w, 64);
+      if (lane == 0) rec[o * Gm::RS + Gm::RS - 1] = prod;
+    }
   }
 }
 
@@ -193,66 +225,76 @@ __device__ __forceinline__ double half_pair_sum(double s) {
   return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
 }
 
-// Per-lane values of one packed reflector record: the segments the lane
-// broadcasts from and tau.
-struct SplitVals {
-  double v0, v1, v2, t;
+// Reflector pairs (A = odd offset o, applied first; B = o-1): the two dot
+// products wA = vA.x and wB = vB.x are taken together on the window as it is
+// before A, and B's is corrected for A's update with the pair coupling
+// c = vB.vA, stored by the packing pass in B's record:
+//   nwA = -tauA wA,  nwB = -tauB (wB + c nwA),  x += vA nwA + vB nwB,
+// which is (I - tauB vB vB^T)(I - tauA vA vA^T) x.  Both reflectors start on
+// register o/2 of each lane half; one reduction across the halves serves the
+// pair.
+struct SplitPair {
+  double a0, a1, a2, ta, b0, b1, tb, c;
 };
 
-// Load the lane's values of reflector record o at Pj (+ z, an SGPR zero that
-// pins the load after the instruction it was derived from).
 template <int NB, int K, int o>
-__device__ __forceinline__ SplitVals split_load(const double* __restrict__ Pj, int voff, int z) {
+__device__ __forceinline__ SplitPair split_load_pair(const double* __restrict__ Pj, int voff,
+                                                     int z) {
   using Gm = SplitGeom<NB, K>;
-  const double* __restrict__ rec = Pj + o * Gm::RS + z;
-  SplitVals s;
-  s.v0 = rec[voff];
-  s.v1 = (Gm::NG == 2) ? rec[voff + 16] : 0.0;
-  s.v2 = (o & 1) ? rec[voff + 16 * Gm::NG] : 0.0;  // extra term: odd offsets only
-  s.t = rec[Gm::HS - 1];
+  static_assert((o & 1) == 1, "A is the odd offset of a pair");
+  const double* __restrict__ ra = Pj + o * Gm::RS + z;
+  const double* __restrict__ rb = ra - Gm::RS;
+  SplitPair s;
+  s.a0 = ra[voff];
+  s.a1 = (Gm::NG == 2) ? ra[voff + 16] : 0.0;
+  s.a2 = ra[voff + 16 * Gm::NG];
+  s.ta = ra[Gm::HS - 1];
+  s.b0 = rb[voff];
+  s.b1 = (Gm::NG == 2) ? rb[voff + 16] : 0.0;
+  s.tb = rb[Gm::HS - 1];
+  s.c = rb[Gm::RS - 1];
   return s;
 }
 
-// One chase step: the K packed reflectors of (block, step) at Pj, offsets
-// o = K-1 .. 0, applied to the window registers x.  voff = lane's offset in a
-// packed record (half * HS + lane % 16).  Reflector values are loaded PD
-// reflectors ahead, issued after the first dot block of the current one.
 template <int NB, int K, int PD, int R>
-__device__ __forceinline__ void step_split(double (&x)[R], const double* __restrict__ Pj,
-                                           int voff) {
+__device__ __forceinline__ void step_split_pair(double (&x)[R], const double* __restrict__ Pj,
+                                                int voff) {
   using Gm = SplitGeom<NB, K>;
+  constexpr int NP = K / 2, HN = Gm::HN, NG = Gm::NG;
   static_assert(R == Gm::R, "window register count");
-  static_assert(PD >= 1 && PD <= 4 && PD < K, "prefetch distance 1..4");
-  constexpr int HN = Gm::HN, NG = Gm::NG;
-  // buf[i] holds reflector K-1-i, then (after each reflector) the next ones
-  SplitVals buf[PD];
+  static_assert(PD >= 1 && PD <= 3 && PD < NP, "pair prefetch distance 1..3");
+  SplitPair buf[PD];
   FwdFor<PD>::run([&](auto ic) {
     constexpr int i = decltype(ic)::value;
-    buf[i] = split_load<NB, K, K - 1 - i>(Pj, voff, 0);
+    buf[i] = split_load_pair<NB, K, K - 1 - 2 * i>(Pj, voff, 0);
   });
-  RevFor<K>::run([&](auto oc) {
-    constexpr int o = decltype(oc)::value;
-    constexpr int p0 = o >> 1;
-    constexpr bool odd = (o & 1) != 0;
-    const SplitVals c0 = buf[0];
-    double a0 = 0.0, a1 = 0.0;
+  RevFor<NP>::run([&](auto pc) {
+    constexpr int pi = decltype(pc)::value;
+    constexpr int p0 = pi;  // (2 pi + 1) >> 1
+    const SplitPair c0 = buf[0];
+    double aA0 = 0.0, aA1 = 0.0, aB0 = 0.0, aB1 = 0.0;
     if constexpr (NG == 2)
-      sdot2_a(a0, a1, c0.v0, c0.v1, &x[p0], &x[p0 + 16]);
+      pdot2_a(aA0, aA1, aB0, aB1, c0.a0, c0.a1, c0.b0, c0.b1, &x[p0], &x[p0 + 16]);
     else
-      sdot1_a(a0, a1, c0.v0, &x[p0]);
-    SplitVals nn{};
-    if constexpr (o - PD >= 0) nn = split_load<NB, K, o - PD>(Pj, voff, zero_after(a0));
+      pdot1_a(aA0, aA1, aB0, aB1, c0.a0, c0.b0, &x[p0]);
+    SplitPair nn{};
+    if constexpr (pi - PD >= 0)
+      nn = split_load_pair<NB, K, 2 * (pi - PD) + 1>(Pj, voff, zero_after(aA0));
     if constexpr (NG == 2)
-      sdot2_b<odd>(a0, a1, c0.v0, c0.v1, c0.v2, &x[p0 + 8], &x[p0 + 24], &x[p0 + HN]);
+      pdot2_b(aA0, aA1, aB0, aB1, c0.a0, c0.a1, c0.b0, c0.b1, c0.a2, &x[p0 + 8], &x[p0 + 24],
+              &x[p0 + HN]);
     else
-      sdot1_b<odd>(a0, a1, c0.v0, c0.v2, &x[p0 + 8], &x[p0 + HN]);
-    const double nw = -(c0.t * half_pair_sum(a0 + a1));
+      pdot1_b(aA0, aA1, aB0, aB1, c0.a0, c0.b0, c0.a2, &x[p0 + 8], &x[p0 + HN]);
+    const double wA = half_pair_sum(aA0 + aA1);
+    const double wB = half_pair_sum(aB0 + aB1);
+    const double nwA = -(c0.ta * wA);
+    const double nwB = -(c0.tb * __builtin_fma(c0.c, nwA, wB));
     if constexpr (NG == 2) {
-      supd2_a(&x[p0], &x[p0 + 16], c0.v0, c0.v1, nw);
-      supd2_b<odd>(&x[p0 + 8], &x[p0 + 24], &x[p0 + HN], c0.v0, c0.v1, c0.v2, nw);
+      pupd2_a(&x[p0], &x[p0 + 16], c0.a0, c0.a1, c0.b0, c0.b1, nwA, nwB);
+      pupd2_b(&x[p0 + 8], &x[p0 + 24], &x[p0 + HN], c0.a0, c0.a1, c0.b0, c0.b1, c0.a2, nwA, nwB);
     } else {
-      supd1_a(&x[p0], c0.v0, nw);
-      supd1_b<odd>(&x[p0 + 8], &x[p0 + HN], c0.v0, c0.v2, nw);
+      pupd1_a(&x[p0], c0.a0, c0.b0, nwA, nwB);
+      pupd1_b(&x[p0 + 8], &x[p0 + HN], c0.a0, c0.b0, c0.a2, nwA, nwB);
     }
     FwdFor<PD - 1>::run([&](auto ic) {
       constexpr int i = decltype(ic)::value;
@@ -362,7 +404,7 @@ __device__ __forceinline__ void run_split_tile(const E* __restrict__ P, int64_t 
       for (int p = R - HN; p < R; ++p) x[p] = rp[p * 64 + lane];
     }
     if constexpr (std::is_same<E, double>::value)
-      step_split<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
+      step_split_pair<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
     else
       step_split_c<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
 #pragma unroll
@@ -590,17 +632,17 @@ size_t split_workspace(int64_t n, int64_t nev) {
 }
 
 #define EHH_SPLIT(E, DT, NB, K, OCC, PD)                                               \
-  {ELPA_PATH_SPLIT, DT, NB, K, OCC, &launch_split<E, NB, K, OCC, PD>,                    \
+  {ELPA_PATH_SPLIT, DT, NB, K, OCC, &launch_split<E, NB, K, OCC, PD>,              \
    &launch_split_batched<E, NB, K, OCC, PD>, &split_workspace<E, NB, K>}
 
 const StripeEntry* split_table(int* size) {
   static const StripeEntry table[] = {
-      EHH_SPLIT(double, 0, 32, 32, 2, 2), EHH_SPLIT(double, 0, 32, 64, 2, 2),
-      EHH_SPLIT(double, 0, 32, 96, 2, 2),
-      // k = 48 and 64 fit three waves per SIMD, k = 80 two (with the values of three
-      // reflectors in flight)
-      EHH_SPLIT(double, 0, 64, 48, 2, 4), EHH_SPLIT(double, 0, 64, 64, 2, 2),
-      EHH_SPLIT(double, 0, 64, 80, 2, 3),
+      EHH_SPLIT(double, 0, 32, 32, 2, 1), EHH_SPLIT(double, 0, 32, 64, 2, 1),
+      EHH_SPLIT(double, 0, 32, 96, 2, 1),
+      // real: reflector pairs, the last number the pairs whose values are in
+      // flight; k = 48 and 64 fit three waves per SIMD, k = 80 two
+      EHH_SPLIT(double, 0, 64, 48, 2, 1), EHH_SPLIT(double, 0, 64, 64, 2, 1),
+      EHH_SPLIT(double, 0, 64, 80, 2, 2),
       // complex: each window register holds two fp64 values
       EHH_SPLIT(z64, 2, 64, 16, 2, 2), EHH_SPLIT(z64, 2, 64, 24, 2, 1),
       EHH_SPLIT(z64, 2, 32, 32, 2, 2), EHH_SPLIT(z64, 2, 32, 48, 2, 1),
