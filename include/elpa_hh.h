@@ -70,11 +70,12 @@ enum {
     ELPA_PATH_STRIPE = 2, /* register-window stripe kernel, k sweeps fused, one lane
                              per column (all element types) */
     ELPA_PATH_SPLIT = 3,  /* register-window stripe kernel, k sweeps fused, two lanes
-                             per column and reflectors pre-packed in consumption order
-                             (real and complex fp64, nbw 32 or 64; their default) */
+                             per column and reflectors pre-packed in consumption order,
+                             real ones applied in pairs (real fp64, fp32 and complex
+                             fp64, nbw 32 or 64; the default) */
     ELPA_PATH_WY = 4      /* compact-WY aggregation of 16 reflectors at a time,
                              applied by MFMA tiles to an LDS-resident window (real fp64
-                             and fp32, nbw 32 or 64; the fp32 default) */
+                             and fp32, nbw 32 or 64) */
 };
 
 /* order of the tiles of one launch over the workgroup ids (elpa_hh_plan.order) */

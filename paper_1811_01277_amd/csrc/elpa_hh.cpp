@@ -92,12 +92,14 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
       return e;
     }
     case ELPA_PATH_AUTO: {
-      // fp64: two-lane VALU kernel; fp32: compact-WY on fp32 MFMA (twice the
-      // VALU rate); complex: one-lane VALU kernel
-      const int order32[] = {ELPA_PATH_WY, ELPA_PATH_STRIPE};
+      // the two-lane VALU kernel where one is compiled (fp64, fp32 and
+      // complex), then for fp32 the compact-WY MFMA path, then the one-lane
+      // kernel
+      const int order32[] = {ELPA_PATH_SPLIT, ELPA_PATH_WY, ELPA_PATH_STRIPE};
       const int order[] = {ELPA_PATH_SPLIT, ELPA_PATH_STRIPE};
       const int* fams = dtype == ELPA_R32 ? order32 : order;
-      for (int f = 0; f < 2; ++f) {
+      const int nf = dtype == ELPA_R32 ? 3 : 2;
+      for (int f = 0; f < nf; ++f) {
         const int fam = fams[f];
         const int kk = k ? k : default_k(fam, dtype, nb);
         const ehh::StripeEntry* e = kk ? find_entry(fam, dtype, nb, kk) : nullptr;

@@ -217,6 +217,132 @@ __device__ __forceinline__ void pupd1_b(double* x, double* xe, double VA0, doubl
                : "v"(VA0), "v"(VB0), "v"(nwA), "v"(nwB), "v"(VA2));
 }
 
+// fp32 pair blocks: the same blocks on 32-bit values (v_fmac_f32 with the
+// same row_newbcast broadcast), for the single-precision split kernel.
+#define EHH_G(D, S, X, L) \
+  "v_fmac_f32_dpp %" #D ", %" #S ", %" #X " row_newbcast:" #L " row_mask:0xf bank_mask:0xf\n"
+#define EHH_PDOT2S(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_G(0, 4, 8, l0) EHH_G(2, 6, 8, l0) EHH_G(1, 5, 16, l0) EHH_G(3, 7, 16, l0) \
+  EHH_G(0, 4, 9, l1) EHH_G(2, 6, 9, l1) EHH_G(1, 5, 17, l1) EHH_G(3, 7, 17, l1) \
+  EHH_G(0, 4, 10, l2) EHH_G(2, 6, 10, l2) EHH_G(1, 5, 18, l2) EHH_G(3, 7, 18, l2) \
+  EHH_G(0, 4, 11, l3) EHH_G(2, 6, 11, l3) EHH_G(1, 5, 19, l3) EHH_G(3, 7, 19, l3) \
+  EHH_G(0, 4, 12, l4) EHH_G(2, 6, 12, l4) EHH_G(1, 5, 20, l4) EHH_G(3, 7, 20, l4) \
+  EHH_G(0, 4, 13, l5) EHH_G(2, 6, 13, l5) EHH_G(1, 5, 21, l5) EHH_G(3, 7, 21, l5) \
+  EHH_G(0, 4, 14, l6) EHH_G(2, 6, 14, l6) EHH_G(1, 5, 22, l6) EHH_G(3, 7, 22, l6) \
+  EHH_G(0, 4, 15, l7) EHH_G(2, 6, 15, l7) EHH_G(1, 5, 23, l7) EHH_G(3, 7, 23, l7)
+#define EHH_PUPD2S(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_G(0, 16, 20, l0) EHH_G(8, 17, 20, l0) \
+  EHH_G(1, 16, 20, l1) EHH_G(9, 17, 20, l1) \
+  EHH_G(2, 16, 20, l2) EHH_G(10, 17, 20, l2) \
+  EHH_G(3, 16, 20, l3) EHH_G(11, 17, 20, l3) \
+  EHH_G(4, 16, 20, l4) EHH_G(12, 17, 20, l4) \
+  EHH_G(5, 16, 20, l5) EHH_G(13, 17, 20, l5) \
+  EHH_G(6, 16, 20, l6) EHH_G(14, 17, 20, l6) \
+  EHH_G(7, 16, 20, l7) EHH_G(15, 17, 20, l7) \
+  EHH_G(0, 18, 21, l0) EHH_G(8, 19, 21, l0) \
+  EHH_G(1, 18, 21, l1) EHH_G(9, 19, 21, l1) \
+  EHH_G(2, 18, 21, l2) EHH_G(10, 19, 21, l2) \
+  EHH_G(3, 18, 21, l3) EHH_G(11, 19, 21, l3) \
+  EHH_G(4, 18, 21, l4) EHH_G(12, 19, 21, l4) \
+  EHH_G(5, 18, 21, l5) EHH_G(13, 19, 21, l5) \
+  EHH_G(6, 18, 21, l6) EHH_G(14, 19, 21, l6) \
+  EHH_G(7, 18, 21, l7) EHH_G(15, 19, 21, l7)
+#define EHH_PUPD2XS(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_G(0, 17, 21, l0) EHH_G(8, 18, 21, l0) \
+  EHH_G(1, 17, 21, l1) EHH_G(9, 18, 21, l1) \
+  EHH_G(2, 17, 21, l2) EHH_G(10, 18, 21, l2) \
+  EHH_G(3, 17, 21, l3) EHH_G(11, 18, 21, l3) \
+  EHH_G(4, 17, 21, l4) EHH_G(12, 18, 21, l4) \
+  EHH_G(5, 17, 21, l5) EHH_G(13, 18, 21, l5) \
+  EHH_G(6, 17, 21, l6) EHH_G(14, 18, 21, l6) \
+  EHH_G(7, 17, 21, l7) EHH_G(15, 18, 21, l7) \
+  EHH_G(0, 19, 22, l0) EHH_G(8, 20, 22, l0) \
+  EHH_G(1, 19, 22, l1) EHH_G(9, 20, 22, l1) \
+  EHH_G(2, 19, 22, l2) EHH_G(10, 20, 22, l2) \
+  EHH_G(3, 19, 22, l3) EHH_G(11, 20, 22, l3) \
+  EHH_G(4, 19, 22, l4) EHH_G(12, 20, 22, l4) \
+  EHH_G(5, 19, 22, l5) EHH_G(13, 20, 22, l5) \
+  EHH_G(6, 19, 22, l6) EHH_G(14, 20, 22, l6) \
+  EHH_G(7, 19, 22, l7) EHH_G(15, 20, 22, l7)
+#define EHH_PDOT1S(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_G(0, 4, 6, l0) EHH_G(2, 5, 6, l0) \
+  EHH_G(1, 4, 7, l1) EHH_G(3, 5, 7, l1) \
+  EHH_G(0, 4, 8, l2) EHH_G(2, 5, 8, l2) \
+  EHH_G(1, 4, 9, l3) EHH_G(3, 5, 9, l3) \
+  EHH_G(0, 4, 10, l4) EHH_G(2, 5, 10, l4) \
+  EHH_G(1, 4, 11, l5) EHH_G(3, 5, 11, l5) \
+  EHH_G(0, 4, 12, l6) EHH_G(2, 5, 12, l6) \
+  EHH_G(1, 4, 13, l7) EHH_G(3, 5, 13, l7)
+#define EHH_PUPD1S(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_G(0, 8, 10, l0) EHH_G(1, 8, 10, l1) EHH_G(2, 8, 10, l2) EHH_G(3, 8, 10, l3) \
+  EHH_G(4, 8, 10, l4) EHH_G(5, 8, 10, l5) EHH_G(6, 8, 10, l6) EHH_G(7, 8, 10, l7) \
+  EHH_G(0, 9, 11, l0) EHH_G(1, 9, 11, l1) EHH_G(2, 9, 11, l2) EHH_G(3, 9, 11, l3) \
+  EHH_G(4, 9, 11, l4) EHH_G(5, 9, 11, l5) EHH_G(6, 9, 11, l6) EHH_G(7, 9, 11, l7)
+#define EHH_PUPD1XS(l0, l1, l2, l3, l4, l5, l6, l7) \
+  EHH_G(0, 9, 11, l0) EHH_G(1, 9, 11, l1) EHH_G(2, 9, 11, l2) EHH_G(3, 9, 11, l3) \
+  EHH_G(4, 9, 11, l4) EHH_G(5, 9, 11, l5) EHH_G(6, 9, 11, l6) EHH_G(7, 9, 11, l7) \
+  EHH_G(0, 10, 12, l0) EHH_G(1, 10, 12, l1) EHH_G(2, 10, 12, l2) EHH_G(3, 10, 12, l3) \
+  EHH_G(4, 10, 12, l4) EHH_G(5, 10, 12, l5) EHH_G(6, 10, 12, l6) EHH_G(7, 10, 12, l7)
+
+// pair dot, two segments: aA0/aA1 += vA . (x, y), aB0/aB1 += vB . (x, y)
+__device__ __forceinline__ void pdot2_a(float& aA0, float& aA1, float& aB0, float& aB1,
+                                        float VA0, float VA1, float VB0, float VB1,
+                                        const float* x, const float* y) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT2S, EHH_LA)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), EHH_VX8(x), EHH_VX8(y));
+}
+__device__ __forceinline__ void pdot2_b(float& aA0, float& aA1, float& aB0, float& aB1,
+                                        float VA0, float VA1, float VB0, float VB1,
+                                        float VA2, const float* x, const float* y,
+                                        const float* xe) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT2S, EHH_LB) EHH_G(0, 24, 25, 0)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), EHH_VX8(x), EHH_VX8(y), "v"(VA2),
+                 "v"(xe[0]));
+}
+// pair update, two segments
+__device__ __forceinline__ void pupd2_a(float* x, float* y, float VA0, float VA1, float VB0,
+                                        float VB1, float nwA, float nwB) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PUPD2S, EHH_LA)
+               : EHH_PX8(x), EHH_PX8(y)
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), "v"(nwA), "v"(nwB));
+}
+__device__ __forceinline__ void pupd2_b(float* x, float* y, float* xe, float VA0, float VA1,
+                                        float VB0, float VB1, float VA2, float nwA,
+                                        float nwB) {
+  asm volatile("s_nop 1\n" EHH_G(16, 23, 21, 0) EHH_X(EHH_PUPD2XS, EHH_LB)
+               : EHH_PX8(x), EHH_PX8(y), "+v"(xe[0])
+               : "v"(VA0), "v"(VA1), "v"(VB0), "v"(VB1), "v"(nwA), "v"(nwB), "v"(VA2));
+}
+// pair dot, one segment (accumulators alternate over the broadcast lanes)
+__device__ __forceinline__ void pdot1_a(float& aA0, float& aA1, float& aB0, float& aB1,
+                                        float VA0, float VB0, const float* x) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT1S, EHH_LA)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VB0), EHH_VX8(x));
+}
+__device__ __forceinline__ void pdot1_b(float& aA0, float& aA1, float& aB0, float& aB1,
+                                        float VA0, float VB0, float VA2, const float* x,
+                                        const float* xe) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PDOT1S, EHH_LB) EHH_G(0, 14, 15, 0)
+               : "+v"(aA0), "+v"(aA1), "+v"(aB0), "+v"(aB1)
+               : "v"(VA0), "v"(VB0), EHH_VX8(x), "v"(VA2), "v"(xe[0]));
+}
+// pair update, one segment
+__device__ __forceinline__ void pupd1_a(float* x, float VA0, float VB0, float nwA,
+                                        float nwB) {
+  asm volatile("s_nop 1\n" EHH_X(EHH_PUPD1S, EHH_LA)
+               : EHH_PX8(x)
+               : "v"(VA0), "v"(VB0), "v"(nwA), "v"(nwB));
+}
+__device__ __forceinline__ void pupd1_b(float* x, float* xe, float VA0, float VB0, float VA2,
+                                        float nwA, float nwB) {
+  asm volatile("s_nop 1\n" EHH_G(8, 13, 11, 0) EHH_X(EHH_PUPD1XS, EHH_LB)
+               : EHH_PX8(x), "+v"(xe[0])
+               : "v"(VA0), "v"(VB0), "v"(nwA), "v"(nwB), "v"(VA2));
+}
+
 // ---------------------------------------------------------------------------
 // Complex (fp64 pairs) split-window blocks.  One segment, broadcast lanes
 // l0..l0+7: dot  a += conj(v) x  (4 FMAs per value, the -Im v term through the

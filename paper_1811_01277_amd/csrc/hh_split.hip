@@ -83,12 +83,12 @@ __device__ __forceinline__ void pack_group(const E* __restrict__ hh, const E* __
     }
     // real records: the second half's spare slot of an even offset holds the
     // pair coupling, written below
-    if (std::is_same<E, double>::value && h == 1 && t == Gm::HS - 1 && (o & 1) == 0) continue;
+    if (std::is_floating_point<E>::value && h == 1 && t == Gm::HS - 1 && (o & 1) == 0) continue;
     rec[e] = v;
   }
-  if constexpr (std::is_same<E, double>::value) {
+  if constexpr (std::is_floating_point<E>::value) {
     // pair coupling c = vB.vA of B = offset o (even) and A = o+1 (vA starts one
-    // window row below vB): one wave per pair, a fixed-order tree sum
+    // window row below vB): one wave per pair, a fixed-order tree sum in fp64
     const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
     for (int o = 2 * wave; o < K; o += 2 * ((int)blockDim.x >> 6)) {
       const int64_t s = s0 + o, sa = s + 1;
@@ -102,12 +102,12 @@ __device__ __forceinline__ void pack_group(const E* __restrict__ hh, const E* __
         if (lane + 1 < lb && lane < la) {
           const int64_t slot_b = ctot - csum(n - 1 - s, NB) + j;
           const int64_t slot_a = ctot - csum(n - 1 - sa, NB) + j;
-          prod = hh[slot_b * NB + lane + 1] * hh[slot_a * NB + lane];
+          prod = (double)hh[slot_b * NB + lane + 1] * (double)hh[slot_a * NB + lane];
         }
       }
 #pragma unroll
       for (int w = 32; w >= 1; w >>= 1) prod += __shfl_xor(prod, w, 64);
-      if (lane == 0) rec[o * Gm::RS + Gm::RS - 1] = prod;
+      if (lane == 0) rec[o * Gm::RS + Gm::RS - 1] = (E)prod;
     }
   }
 }
@@ -225,6 +225,15 @@ __device__ __forceinline__ double half_pair_sum(double s) {
   return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
 }
 
+__device__ __forceinline__ float half_pair_sum(float s) {
+  const unsigned u = __float_as_uint(s);
+  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
 // Reflector pairs (A = odd offset o, applied first; B = o-1): the two dot
 // products wA = vA.x and wB = vB.x are taken together on the window as it is
 // before A, and B's is corrected for A's update with the pair coupling
@@ -233,37 +242,38 @@ __device__ __forceinline__ double half_pair_sum(double s) {
 // which is (I - tauB vB vB^T)(I - tauA vA vA^T) x.  Both reflectors start on
 // register o/2 of each lane half; one reduction across the halves serves the
 // pair.
+template <typename T>
 struct SplitPair {
-  double a0, a1, a2, ta, b0, b1, tb, c;
+  T a0, a1, a2, ta, b0, b1, tb, c;
 };
 
-template <int NB, int K, int o>
-__device__ __forceinline__ SplitPair split_load_pair(const double* __restrict__ Pj, int voff,
-                                                     int z) {
+template <int NB, int K, int o, typename T>
+__device__ __forceinline__ SplitPair<T> split_load_pair(const T* __restrict__ Pj, int voff,
+                                                        int z) {
   using Gm = SplitGeom<NB, K>;
   static_assert((o & 1) == 1, "A is the odd offset of a pair");
-  const double* __restrict__ ra = Pj + o * Gm::RS + z;
-  const double* __restrict__ rb = ra - Gm::RS;
-  SplitPair s;
+  const T* __restrict__ ra = Pj + o * Gm::RS + z;
+  const T* __restrict__ rb = ra - Gm::RS;
+  SplitPair<T> s;
   s.a0 = ra[voff];
-  s.a1 = (Gm::NG == 2) ? ra[voff + 16] : 0.0;
+  s.a1 = (Gm::NG == 2) ? ra[voff + 16] : T(0);
   s.a2 = ra[voff + 16 * Gm::NG];
   s.ta = ra[Gm::HS - 1];
   s.b0 = rb[voff];
-  s.b1 = (Gm::NG == 2) ? rb[voff + 16] : 0.0;
+  s.b1 = (Gm::NG == 2) ? rb[voff + 16] : T(0);
   s.tb = rb[Gm::HS - 1];
   s.c = rb[Gm::RS - 1];
   return s;
 }
 
-template <int NB, int K, int PD, int R>
-__device__ __forceinline__ void step_split_pair(double (&x)[R], const double* __restrict__ Pj,
-                                                int voff) {
+// T = double or float (the same blocks on 64- or 32-bit values)
+template <int NB, int K, int PD, typename T, int R>
+__device__ __forceinline__ void step_split_pair(T (&x)[R], const T* __restrict__ Pj, int voff) {
   using Gm = SplitGeom<NB, K>;
   constexpr int NP = K / 2, HN = Gm::HN, NG = Gm::NG;
   static_assert(R == Gm::R, "window register count");
   static_assert(PD >= 1 && PD <= 3 && PD < NP, "pair prefetch distance 1..3");
-  SplitPair buf[PD];
+  SplitPair<T> buf[PD];
   FwdFor<PD>::run([&](auto ic) {
     constexpr int i = decltype(ic)::value;
     buf[i] = split_load_pair<NB, K, K - 1 - 2 * i>(Pj, voff, 0);
@@ -271,13 +281,13 @@ __device__ __forceinline__ void step_split_pair(double (&x)[R], const double* __
   RevFor<NP>::run([&](auto pc) {
     constexpr int pi = decltype(pc)::value;
     constexpr int p0 = pi;  // (2 pi + 1) >> 1
-    const SplitPair c0 = buf[0];
-    double aA0 = 0.0, aA1 = 0.0, aB0 = 0.0, aB1 = 0.0;
+    const SplitPair<T> c0 = buf[0];
+    T aA0 = T(0), aA1 = T(0), aB0 = T(0), aB1 = T(0);
     if constexpr (NG == 2)
       pdot2_a(aA0, aA1, aB0, aB1, c0.a0, c0.a1, c0.b0, c0.b1, &x[p0], &x[p0 + 16]);
     else
       pdot1_a(aA0, aA1, aB0, aB1, c0.a0, c0.b0, &x[p0]);
-    SplitPair nn{};
+    SplitPair<T> nn{};
     if constexpr (pi - PD >= 0)
       nn = split_load_pair<NB, K, 2 * (pi - PD) + 1>(Pj, voff, zero_after(aA0));
     if constexpr (NG == 2)
@@ -285,10 +295,10 @@ __device__ __forceinline__ void step_split_pair(double (&x)[R], const double* __
               &x[p0 + HN]);
     else
       pdot1_b(aA0, aA1, aB0, aB1, c0.a0, c0.b0, c0.a2, &x[p0 + 8], &x[p0 + HN]);
-    const double wA = half_pair_sum(aA0 + aA1);
-    const double wB = half_pair_sum(aB0 + aB1);
-    const double nwA = -(c0.ta * wA);
-    const double nwB = -(c0.tb * __builtin_fma(c0.c, nwA, wB));
+    const T wA = half_pair_sum(aA0 + aA1);
+    const T wB = half_pair_sum(aB0 + aB1);
+    const T nwA = -(c0.ta * wA);
+    const T nwB = -(c0.tb * fma_t(c0.c, nwA, wB));
     if constexpr (NG == 2) {
       pupd2_a(&x[p0], &x[p0 + 16], c0.a0, c0.a1, c0.b0, c0.b1, nwA, nwB);
       pupd2_b(&x[p0 + 8], &x[p0 + 24], &x[p0 + HN], c0.a0, c0.a1, c0.b0, c0.b1, c0.a2, nwA, nwB);
@@ -403,7 +413,7 @@ __device__ __forceinline__ void run_split_tile(const E* __restrict__ P, int64_t 
 #pragma unroll
       for (int p = R - HN; p < R; ++p) x[p] = rp[p * 64 + lane];
     }
-    if constexpr (std::is_same<E, double>::value)
+    if constexpr (std::is_same<E, double>::value || std::is_same<E, float>::value)
       step_split_pair<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
     else
       step_split_c<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
@@ -643,6 +653,11 @@ const StripeEntry* split_table(int* size) {
       // flight; k = 48 and 64 fit three waves per SIMD, k = 80 two
       EHH_SPLIT(double, 0, 64, 48, 2, 1), EHH_SPLIT(double, 0, 64, 64, 2, 1),
       EHH_SPLIT(double, 0, 64, 80, 2, 2),
+      // fp32: one register per value, up to four waves per SIMD
+      EHH_SPLIT(float, 1, 64, 64, 4, 2), EHH_SPLIT(float, 1, 64, 80, 4, 2),
+      EHH_SPLIT(float, 1, 64, 96, 4, 1),
+      EHH_SPLIT(float, 1, 32, 64, 4, 2), EHH_SPLIT(float, 1, 32, 96, 4, 2),
+      EHH_SPLIT(float, 1, 32, 128, 3, 1),
       // complex: each window register holds two fp64 values
       EHH_SPLIT(z64, 2, 64, 16, 2, 2), EHH_SPLIT(z64, 2, 64, 24, 2, 1),
       EHH_SPLIT(z64, 2, 32, 32, 2, 2), EHH_SPLIT(z64, 2, 32, 48, 2, 1),

@@ -114,7 +114,10 @@ def test_plan_support_table():
     for nbw, k in [(64, 48), (64, 64), (64, 80), (32, 32), (32, 64), (32, 96)]:
         assert P.plan_supported(nbw, P.R64, P.PATH_SPLIT, k), (nbw, k)
     assert P.plan_supported(64, P.R64, P.PATH_SPLIT)          # library default k
-    assert not P.plan_supported(64, P.R32, P.PATH_SPLIT, 64)
+    # fp32 two-lane kernel (four waves per SIMD): nbw 64 with k 64..96, nbw 32 up to 128
+    for nbw, k in [(64, 64), (64, 80), (64, 96), (32, 64), (32, 96), (32, 128)]:
+        assert P.plan_supported(nbw, P.R32, P.PATH_SPLIT, k), (nbw, k)
+    assert not P.plan_supported(64, P.R32, P.PATH_SPLIT, 48)
     assert P.plan_supported(64, P.C64, P.PATH_SPLIT)           # complex: k = 24 default
     assert P.plan_supported(64, P.C64, P.PATH_SPLIT, 16)
     assert not P.plan_supported(64, P.C64, P.PATH_SPLIT, 80)
@@ -157,6 +160,8 @@ def test_workspace_bytes():
     two = P.workspace_bytes_batched([(n, nev, nbw, P.R64), (500, 300, 32, P.R32)])
     assert two > one
     assert P.workspace_bytes_batched([(500, 300, 32, P.R32)]) >= \
+        P.workspace_bytes(500, 300, 32, P.R32)
+    assert P.workspace_bytes_batched([(500, 300, 32, P.R32)], path=P.PATH_WY) >= \
         P.workspace_bytes(500, 300, 32, P.R32, P.PATH_WY)
     assert P.workspace_bytes_batched([(500, 300, 0, P.R32)]) == -1
     assert P.workspace_bytes_batched([]) == 0

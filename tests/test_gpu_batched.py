@@ -74,11 +74,14 @@ def test_batch_matches_oracle_and_single_calls(torch_dev):
         assert torch.equal(q, s), "batched result differs from the single call"
 
 
-def test_fp32_batch_on_wy_path_equals_single_calls(torch_dev):
-    """fp32 problems (library choice: the compact-WY MFMA path) give bitwise the
-    same result in a batch as alone, and match the oracle."""
+@pytest.mark.parametrize("family", ["default", "wy"])
+def test_fp32_batch_equals_single_calls(torch_dev, family):
+    """fp32 problems (library choice: the two-lane kernel; and the compact-WY
+    MFMA path) give bitwise the same result in a batch as alone, and match the
+    oracle."""
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
+    path = P.PATH_WY if family == "wy" else None
     sizes = [(300, 64, 150), (517, 64, 517), (130, 32, 33), (260, 64, 97)]
     probs, host = [], []
     for i, (n, nbw, nev) in enumerate(sizes):
@@ -88,11 +91,11 @@ def test_fp32_batch_on_wy_path_equals_single_calls(torch_dev):
     singles = []
     for (q, h, t, nbw) in probs:
         qq = q.clone()
-        P.hh_trafo(qq, h, t, nbw)
+        P.hh_trafo(qq, h, t, nbw, path=path)
         singles.append(qq)
     P.profile_enable(True)
     try:
-        P.hh_trafo_batched(probs)
+        P.hh_trafo_batched(probs, path=path)
         pr = P.profile_last()
     finally:
         P.profile_enable(False)

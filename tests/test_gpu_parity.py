@@ -20,7 +20,7 @@ pytestmark = pytest.mark.gpu
 
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
 KS = [1, 2, 4, 6, 8, 16, 24, 32, 40, 48, 64]
-SPLIT_KS = [16, 24, 32, 48, 64, 80, 96]
+SPLIT_KS = [16, 24, 32, 48, 64, 80, 96, 128]
 WY_KS = [32, 48, 64, 96]
 
 
@@ -216,6 +216,26 @@ def test_wy_path_tilings(torch_dev, dt, nbw, k):
         print(f"wy n={n} nbw={nbw} k={k} dt={dt} steps={steps} streams={ns}", flush=True)
         got = run_gpu(torch, dev, hh, tau, Z, nbw, dt, P.PATH_WY, k, steps=steps, streams=ns)
         assert checks.max_rel_err(got, ref) <= TOL[dt], steps
+        outs.append(got)
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+@pytest.mark.parametrize("nbw,k", [(64, 64), (64, 80), (64, 96), (32, 64), (32, 96), (32, 128)])
+def test_split_fp32_tilings(torch_dev, nbw, k):
+    """Two-lane kernel on fp32 values (reflector pairs): tiles of 1, 3 and 16
+    chase steps and two stripe groups give bitwise equal results that match
+    the oracle on the fp32-rounded inputs."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nev = 900, 77
+    hh, tau, Z = oracle_inputs(n, nbw, nev, "r32", 151 + k)
+    ref = bt.bt_tridiag_to_band(rounded(hh, "r32"), rounded(tau, "r32"), rounded(Z, "r32"), n, nbw)
+    outs = []
+    for steps, ns in ((1, 1), (3, 1), (16, 2)):
+        print(f"split r32 n={n} nbw={nbw} k={k} steps={steps} streams={ns}", flush=True)
+        got = run_gpu(torch, dev, hh, tau, Z, nbw, "r32", P.PATH_SPLIT, k, steps=steps,
+                      streams=ns)
+        assert checks.max_rel_err(got, ref) <= TOL["r32"], steps
         outs.append(got)
     assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
 
