@@ -241,12 +241,29 @@ def cpu_baseline(args, hh, tau, Z):
     ncols = max(ncal, (ncols // (8 * thr)) * 8 * thr)
     ncols = min(ncols, Z.shape[1])
     t0 = time.perf_counter()
-    bt.bt_tridiag_to_band(hh, tau, np.asfortranarray(Z[:, :ncols]), n, nbw, nthreads=thr)
+    ref = bt.bt_tridiag_to_band(hh, tau, np.asfortranarray(Z[:, :ncols]), n, nbw, nthreads=thr)
     dt = time.perf_counter() - t0
     return {"value": round(per_col * ncols / dt / 1e9, 3), "unit": "GFLOP/s", "cores": thr,
             "kind": "oracle",
             "sample": f"{ncols} of {Z.shape[1]} columns, all {n}x{n} nbw={nbw} reflectors, "
-                      f"{dt:.1f} s, fp64 C oracle (OpenMP over 8-column blocks)"}
+                      f"{dt:.1f} s, fp64 C oracle (OpenMP over 8-column blocks)"}, ref
+
+
+def accuracy(gpu_cols, ref, dt):
+    """The GPU result of one call in the timed configuration against the
+    oracle on the cpu_baseline leg's columns (fp64 inputs; for fp32 this is the
+    fp32 error against the fp64 oracle)."""
+    from oracle import checks
+    m = min(gpu_cols.shape[1], ref.shape[1])
+    err = checks.max_rel_err(gpu_cols[:, :m].astype(ref.dtype), ref[:, :m])
+    out = {"columns": m, "max_rel_err_vs_fp64_oracle": float(f"{err:.3e}"),
+           "measure": "max |gpu - oracle| / max |oracle| over the sampled columns"}
+    if dt == "r32":
+        out["note"] = ("fp32 inputs are the fp64 ones rounded; the 5e-5 parity bound of the "
+                       "tests applies against the oracle on the rounded inputs")
+    else:
+        out["tol"] = 1e-12
+    return out
 
 
 def main():
@@ -332,6 +349,14 @@ def main():
                      "flops_per_launch": flops / launches,
                      "call_ms": [round(x, 3) for x in per]},
     }
+    gpu_cols = None
+    if not args.no_cpu:
+        # one fresh call in the timed configuration; its first columns are
+        # checked against the oracle run of the cpu_baseline leg
+        q.copy_(torch.from_numpy(np.ascontiguousarray(Z.T).astype(npdt)).t())
+        P.hh_trafo(q, h, t, nbw, stream=stream, **plan)
+        torch.cuda.synchronize()
+        gpu_cols = q[:, :min(nev, 4096)].cpu().numpy()
     del q, h, t
     torch.cuda.empty_cache()
     if not args.no_batched:
@@ -341,7 +366,8 @@ def main():
         out["served_stream"] = served_stream(args)
         torch.cuda.empty_cache()
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(args, hh, tau, Z)
+        out["cpu_baseline"], ref = cpu_baseline(args, hh, tau, Z)
+        out["accuracy"] = accuracy(gpu_cols, ref, dt)
     print(json.dumps(out), flush=True)
 
 
