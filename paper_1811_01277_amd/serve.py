@@ -14,11 +14,12 @@ computation runs in the HIP library):
 * admission by device-memory footprint: a request is launched only while
   the library's workspace for the in-flight work
   (elpa_hh_workspace_bytes_batched) stays within the budget;
-* continuous batching: `slots` streams; whenever a slot is free, every ready
-  request that fits the budget (up to max_batch, oldest first) is launched
-  on it as one elpa_hh_trafo_batched call, so requests that arrive while
-  others run are admitted as soon as a slot and memory free up and their work
-  overlaps on the device;
+* continuous batching: `slots` streams; whenever a slot is free, ready
+  requests that fit the budget (oldest first, at most max_batch and at most
+  an equal share of the ready requests per free slot) are launched on it as
+  one elpa_hh_trafo_batched call, so requests that arrive while others run
+  are admitted as soon as a slot and memory free up and their work overlaps
+  on the device;
 * a lone request on an otherwise idle device runs as a single call with the
   library's stripe-group streams (the batched call keeps to its slot's
   stream, so concurrent slots never share the library's streams);
@@ -125,12 +126,17 @@ class Server:
             for i, b in enumerate(busy):
                 if b is not None or not ready:
                     continue
+                # spread the ready requests over the free slots before
+                # batching them: a request batched with larger ones waits for
+                # them, while one on a slot of its own overlaps with them
+                free = sum(x is None for x in busy)
+                cap = min(self.max_batch, -(-len(ready) // free))
                 batch, nbytes, rest = [], 0, []
                 for r in ready:
                     f = footprint(r)
                     fits = in_use + nbytes + f <= self.budget
                     # an idle device always takes the oldest request
-                    if len(batch) < self.max_batch and (fits or (in_use == 0 and not batch)):
+                    if len(batch) < cap and (fits or (in_use == 0 and not batch)):
                         batch.append(r)
                         nbytes += f
                     else:

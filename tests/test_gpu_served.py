@@ -61,7 +61,8 @@ def test_served_results_equal_alone_and_overlap(torch_dev):
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
     from paper_1811_01277_amd.serve import Server, latency_stats
-    reqs, host = make_stream(torch, dev)
+    # arrivals close together: more ready requests than slots, so batches form
+    reqs, host = make_stream(torch, dev, rate=1e5)
     inputs = [r.q.clone() for r in reqs]
     print(f"served: {len(reqs)} requests", flush=True)
     srv = Server(dev, slots=3, max_batch=8)
