@@ -67,6 +67,10 @@ def library():
         L.elpa_hh_workspace_bytes_batched.restype = i64
         L.elpa_hh_tune.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, i32, C.POINTER(_Plan)]
         L.elpa_hh_tune.restype = C.c_int
+        L.elpa_bt2_trafo.argtypes = [i64, i64, i64, p, i64, p, p, i64, i32, p, i64]
+        L.elpa_bt2_trafo.restype = C.c_int
+        L.elpa_bt2_workspace_bytes.argtypes = [i64, i64, i64, i32, i64]
+        L.elpa_bt2_workspace_bytes.restype = i64
         L.elpa_hh_tune_batched.argtypes = [C.POINTER(_Problem), i64, p, i32, C.POINTER(_Plan)]
         L.elpa_hh_tune_batched.restype = C.c_int
         L.elpa_hh_tuner_set.argtypes = [i32, i64, i64, i64, C.POINTER(_Plan)]
@@ -325,3 +329,51 @@ def tune_batched(problems, level=0, stream=None):
     _check(library().elpa_hh_tune_batched(arr, len(problems), C.c_void_p(st), level,
                                            C.byref(out)))
     return _plan_dict(out)
+
+
+def bt2_trafo(q, v, tau, nbw, stream=None, block=0):
+    """Band -> full back-transformation Q <- H_0 ... H_{n-nbw-1} Q in place
+    (include/elpa_bt2.h).
+
+    q:   (n, nev) column-major device tensor (float64, float32, complex128).
+    v:   column-major device tensor with n rows (leading dimension
+         v.stride(1) >= n) and at least n - nbw columns; column c holds v_c on
+         rows c+nbw+1 .. n-1 (its unit lead at row c+nbw and everything above
+         are not read).
+    tau: 1-D contiguous tensor of at least n - nbw scalars (same dtype).
+    block: reflectors per compact-WY block (0 = library choice).
+    """
+    import torch
+    if q.dim() != 2 or v.dim() != 2:
+        raise ValueError("q and v must be 2-D")
+    n, nev = q.shape
+    if n > 1 and nev > 0 and q.stride(0) != 1:
+        raise ValueError("q must be column major (stride(0) == 1)")
+    if v.shape[0] != n or (v.shape[1] > 1 and v.stride(0) != 1):
+        raise ValueError("v must be column major with n rows")
+    nref = max(0, n - nbw)
+    if v.shape[1] < nref or tau.numel() < nref:
+        raise ValueError("v needs %d columns and tau %d elements" % (nref, nref))
+    if v.dtype != q.dtype or tau.dtype != q.dtype:
+        raise TypeError("q, v and tau must share a dtype")
+    if not tau.is_contiguous():
+        raise ValueError("tau must be contiguous")
+    ldq = q.stride(1) if nev > 1 else max(n, 1)
+    ldv = v.stride(1) if v.shape[1] > 1 else max(n, 1)
+    if stream is None:
+        st = torch.cuda.current_stream(q.device).cuda_stream if q.is_cuda else 0
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = stream.cuda_stream
+    rc = int(library().elpa_bt2_trafo(n, nev, nbw, C.c_void_p(v.data_ptr()), ldv,
+                                      C.c_void_p(tau.data_ptr()), C.c_void_p(q.data_ptr()), ldq,
+                                      _dtype_code(q), C.c_void_p(st), int(block)))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    return q
+
+
+def bt2_workspace_bytes(n, nev, nbw, dtype, block=0):
+    """Device bytes one bt2_trafo call allocates (-1: invalid)."""
+    return int(library().elpa_bt2_workspace_bytes(n, nev, nbw, dtype, block))

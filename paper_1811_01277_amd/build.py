@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libelpahip.so")
-SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_split.hip", "hh_wy.hip"]
+SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_split.hip", "hh_wy.hip", "bt2.hip"]
 ARCH = os.environ.get("ELPA_HIP_ARCH", "gfx950")
 
 FLAGS = [
@@ -47,7 +47,8 @@ def build(verbose=False, jobs=None):
         with ThreadPoolExecutor(max_workers=jobs or len(cmds)) as ex:
             list(ex.map(lambda c: _run(c, verbose), cmds))
         tmp = LIB + ".tmp" + tag
-        _run(["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp], verbose)
+        _run(["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp,
+              "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"], verbose)
         os.replace(tmp, LIB)
     finally:
         for o in objs:

@@ -1,12 +1,13 @@
 """Host-side tests of the C ABI (no GPU needed, no compute call is made).
 
-* The library loads and exports every function include/elpa_hh.h declares.
+* The library loads and exports every function include/*.h declares.
 * Slot arithmetic equals a brute-force enumeration.
 * Every invalid argument returns its error code before anything is enqueued
   (checked with host buffers that must stay untouched), n <= 1 and nev == 0
   are no-ops.
 """
 import ctypes as C
+import glob
 import os
 import re
 import subprocess
@@ -20,15 +21,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def header_functions():
-    src = open(os.path.join(ROOT, "include", "elpa_hh.h")).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(elpa_\w+)\s*\(", src)))
+    names = set()
+    for h in sorted(glob.glob(os.path.join(ROOT, "include", "*.h"))):
+        src = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(elpa_\w+)\s*\(", src))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     lib = P.library()
     names = header_functions()
-    assert "elpa_hh_trafo" in names and len(names) >= 7
+    assert "elpa_hh_trafo" in names and "elpa_bt2_trafo" in names and len(names) >= 9
     for nm in names:
         assert hasattr(lib, nm), nm
     out = subprocess.run(["nm", "-D", "--defined-only", P.library_path()],
@@ -173,3 +176,27 @@ def test_profile_api_without_calls():
         P.profile_last()                  # nothing recorded
     assert e.value.code == -1
     assert P.strerror(12345) == "unknown error code"
+
+
+def test_bt2_argument_errors_and_workspace():
+    """Band -> full back-transformation: argument checks run before anything
+    touches a device; no-op sizes succeed; workspace sizes."""
+    lib = P.library()
+    nul = None
+    # n <= nbw or nev == 0: nothing to do
+    assert lib.elpa_bt2_trafo(64, 10, 64, nul, 64, nul, nul, 64, P.R64, nul, 0) == 0
+    assert lib.elpa_bt2_trafo(100, 0, 32, nul, 100, nul, nul, 100, P.R64, nul, 0) == 0
+    assert lib.elpa_bt2_trafo(100, 5, 32, nul, 100, nul, nul, 100, 7, nul, 0) == -2
+    assert lib.elpa_bt2_trafo(100, 5, 0, nul, 100, nul, nul, 100, P.R64, nul, 0) == -1
+    assert lib.elpa_bt2_trafo(100, 5, 32, nul, 100, nul, nul, 99, P.R64, nul, 0) == -1   # ldq
+    assert lib.elpa_bt2_trafo(100, 5, 32, nul, 99, nul, nul, 100, P.R64, nul, 0) == -1   # ldv
+    assert lib.elpa_bt2_trafo(100, 5, 32, nul, 100, nul, nul, 100, P.R64, nul, 0) == -1  # nulls
+    assert lib.elpa_bt2_trafo(100, 5, 32, nul, 100, nul, nul, 100, P.R64, nul, 513) == -1
+    assert P.bt2_workspace_bytes(100, 5, 32, P.R64) > 0
+    assert P.bt2_workspace_bytes(32, 5, 32, P.R64) == 0
+    assert P.bt2_workspace_bytes(100, 5, 32, 9) == -1
+    # V block (68 x 64) + G + M (64 x 64 each) + W (64 x 5) + partial products
+    # (68 rows: one K chunk, the larger of W's and G's), 256-byte aligned
+    al = lambda x: -(-x // 256) * 256
+    assert P.bt2_workspace_bytes(100, 5, 32, P.R64, 64) == \
+        al(68 * 64 * 8) + 2 * al(64 * 64 * 8) + al(64 * 5 * 8) + al(64 * 64 * 8)

@@ -30,6 +30,7 @@ differ, the shapes, sizes, slot structure and magnitudes do not.
 import numpy as np
 
 __all__ = [
+    "synthetic_stage1",
     "sym_gaussian", "herm_gaussian", "haar_spectrum", "reflector_layout",
     "synthetic_reflectors", "gaussian_block", "to_dtype",
     "batched_sizes", "scf_sequence_sizes", "scf_trace",
@@ -183,3 +184,34 @@ def device_block(torch, n, nev, device, generator, dtype=None):
     z = torch.randn((nev, n), generator=generator, device=device, dtype=torch.float64)
     z *= 1.0 / np.sqrt(n)
     return z.to(dtype or torch.float64).t()
+
+
+def synthetic_stage1(n, b, complex_=False, seed=0):
+    """Random first-stage (full -> band) reflectors in the layout of the band
+    -> full back-transformation: V (n x max(n-b, 1), column major) with
+    column c holding v_c on rows c+b .. n-1 (unit lead at row c+b, entries
+    of scale 1/sqrt(n-c-b) below, zeros above), tau (max(n-b, 1),) with
+    tau = 2 / |v|^2 (real) or (1 - e^{i theta}) / |v|^2 (complex), so every
+    H_c = I - tau v v^H is unitary.
+    """
+    N = max(n - b, 0)
+    g = _rng(seed)
+    dt = np.complex128 if complex_ else np.float64
+    V = np.zeros((n, max(N, 1)), dtype=dt, order="F")
+    tau = np.zeros(max(N, 1), dtype=dt)
+    for c in range(N):
+        L = n - c - b
+        sc = 1.0 / np.sqrt(L)
+        if complex_:
+            h = np.sqrt(0.5) * sc
+            v = g.standard_normal(L) * h + 1j * (g.standard_normal(L) * h)
+        else:
+            v = g.standard_normal(L) * sc
+        v[0] = 1.0
+        V[c + b:, c] = v
+        nrm2 = float(np.sum(np.abs(v) ** 2))
+        if complex_:
+            tau[c] = (1.0 - np.exp(1j * g.uniform(0.0, 2.0 * np.pi))) / nrm2
+        else:
+            tau[c] = 2.0 / nrm2
+    return V, tau
