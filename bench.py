@@ -49,6 +49,11 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
     ap.add_argument("--no-served", action="store_true", help="skip the served SCF stream leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload leg")
+    ap.add_argument("--no-bt2", action="store_true",
+                    help="skip the band->full back-transformation leg")
+    ap.add_argument("--bt2-only", action="store_true",
+                    help="instead of the benchmark: only the band->full leg at --nev "
+                         "(for profiling it on its own)")
     ap.add_argument("--served-rates", default="120,250",
                     help="Poisson arrival rates of the served stream (requests / s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -169,6 +174,46 @@ def batched_workload():
             "gflops_one_call_per_problem": round(flops / t_single / 1e6, 1)}
 
 
+def bt2_leg(args, nevs=None):
+    """Band -> full back-transformation (elpa_bt2_trafo) on the same n and
+    nev: synthetic first-stage reflectors (workload.synthetic_stage1, nbw 64),
+    real fp64, the library's default block; counted flops 2 nev N (N+1) with
+    N = n - nbw (4 (n - c - nbw) nev per reflector c).  The products run on the
+    fp64 matrix cores, so the roofline is the 78.6 TFLOP/s MFMA peak."""
+    import torch
+    import workload as W
+    import paper_1811_01277_amd as P
+    dev = torch.device("cuda:0")
+    n, nbw = args.n, 64
+    out = {"workload": f"band->full back-transform, n={n}, nbw={nbw}, r64, synthetic "
+                       f"first-stage reflectors", "runs": []}
+    V, tau = W.synthetic_stage1(n, nbw, seed=args.seed + 7)
+    v = torch.from_numpy(np.ascontiguousarray(V.T)).to(dev).t()
+    t = torch.from_numpy(tau).to(dev)
+    del V
+    N = n - nbw
+    for nev in nevs or sorted({args.nev, min(args.nev, 2000)}, reverse=True):
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed + 8)
+        q = torch.randn(nev, n, device=dev, dtype=torch.float64, generator=g).t()
+        P.bt2_trafo(q, v, t, nbw)
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        reps = 2
+        ev[0].record()
+        for _ in range(reps):
+            P.bt2_trafo(q, v, t, nbw)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        fl = 2.0 * nev * N * (N + 1)
+        out["runs"].append({"nev": nev, "ms": round(ms, 3), "gflops": round(fl / ms / 1e6, 1),
+                            "frac_fp64_mfma_peak": round(fl / ms / 1e9 / 78.6, 4)})
+        del q
+        torch.cuda.empty_cache()
+    return out
+
+
 def recorded_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (profiles/*_traffic.json), if they were taken
@@ -271,6 +316,9 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.bt2_only:
+        print(json.dumps({"bt2": bt2_leg(args, [args.nev])}), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(the path shards by columns across GPUs by design, "
@@ -361,6 +409,9 @@ def main():
     torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched_workload"] = batched_workload()
+        torch.cuda.empty_cache()
+    if not args.no_bt2:
+        out["bt2"] = bt2_leg(args)
         torch.cuda.empty_cache()
     if not args.no_served:
         out["served_stream"] = served_stream(args)

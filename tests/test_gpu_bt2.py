@@ -110,7 +110,7 @@ def test_bt2_parity_blocks(torch_dev, case, dt):
     Vr = np.where(np.isnan(V), 0, V)
     ref = bt.bt_band_to_full(abi_to_panels(rounded(Vr, dt), rounded(tau, dt), n, nbw),
                              rounded(Z, dt), nbw)
-    for block in (0, 1, 7, 64, 128):
+    for block in (0, 1, 7, 64, 128, 512):
         print(f"bt2 n={n} nbw={nbw} nev={nev} dt={dt} block={block}", flush=True)
         got = run_gpu(torch, dev, V, tau, Z, nbw, dt, block)
         assert np.all(np.isfinite(got)), "a NaN entry of V was read"
@@ -163,9 +163,9 @@ def test_eigenvector_chain_on_gpu(torch_dev, cplx):
 
 
 def test_bt2_full_size_sampled(torch_dev):
-    """n = 20000, nbw = 64, nev = 2000 (the library's default block of 384), synthetic
-    unit-lead reflectors with tau = 2 / |v|^2; four sampled columns against
-    the oracle."""
+    """n = 20000, nbw = 64, nev = 2000 with the library's default block (384
+    reflectors), synthetic unit-lead reflectors with tau = 2 / |v|^2; four
+    sampled columns against the oracle."""
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
     n, nbw, nev = 20000, 64, 2000
