@@ -67,6 +67,8 @@ def library():
         L.elpa_hh_workspace_bytes_batched.restype = i64
         L.elpa_hh_tune.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, i32, C.POINTER(_Plan)]
         L.elpa_hh_tune.restype = C.c_int
+        L.elpa_band_to_tridiag.argtypes = [i64, i64, p, i64, p, p, p, p, i32, p]
+        L.elpa_band_to_tridiag.restype = C.c_int
         L.elpa_bt2_trafo.argtypes = [i64, i64, i64, p, i64, p, p, i64, i32, p, i64]
         L.elpa_bt2_trafo.restype = C.c_int
         L.elpa_bt2_workspace_bytes.argtypes = [i64, i64, i64, i32, i64]
@@ -377,3 +379,41 @@ def bt2_trafo(q, v, tau, nbw, stream=None, block=0):
 def bt2_workspace_bytes(n, nev, nbw, dtype, block=0):
     """Device bytes one bt2_trafo call allocates (-1: invalid)."""
     return int(library().elpa_bt2_workspace_bytes(n, nev, nbw, dtype, block))
+
+
+def band_to_tridiag(a, nbw, stream=None):
+    """Band -> tridiagonal reduction on the device (include/elpa_b2t.h).
+
+    a: (n, n) column-major device tensor (float64 or complex128), a Hermitian
+       band matrix of semi-bandwidth nbw in full storage; overwritten.
+    Returns (d, e, hh, tau): float64 device tensors of the diagonal (n) and
+    subdiagonal (n-1), and the reflectors in hh_trafo's layout (tensors of
+    a's dtype), all produced on the device.
+    """
+    import torch
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be square")
+    n = a.shape[0]
+    if n > 1 and a.stride(0) != 1:
+        raise ValueError("a must be column major (stride(0) == 1)")
+    lda = a.stride(1) if n > 1 else 1
+    nr = num_reflectors(n, nbw) if n > 1 else 0
+    dev = a.device
+    d = torch.empty(n, dtype=torch.float64, device=dev)
+    e = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
+    hh = torch.empty(max(nr * nbw, 1), dtype=a.dtype, device=dev)
+    tau = torch.empty(max(nr, 1), dtype=a.dtype, device=dev)
+    if stream is None:
+        st = torch.cuda.current_stream(dev).cuda_stream if a.is_cuda else 0
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = stream.cuda_stream
+    rc = int(library().elpa_band_to_tridiag(n, nbw, C.c_void_p(a.data_ptr()), lda,
+                                            C.c_void_p(d.data_ptr()), C.c_void_p(e.data_ptr()),
+                                            C.c_void_p(hh.data_ptr()),
+                                            C.c_void_p(tau.data_ptr()), _dtype_code(a),
+                                            C.c_void_p(st)))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    return d, e[:max(n - 1, 0)], hh[:nr * nbw], tau[:nr]

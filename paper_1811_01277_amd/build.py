@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libelpahip.so")
-SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_split.hip", "hh_wy.hip", "bt2.hip"]
+SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_split.hip", "hh_wy.hip", "bt2.hip",
+           "b2t.hip"]
 ARCH = os.environ.get("ELPA_HIP_ARCH", "gfx950")
 
 FLAGS = [

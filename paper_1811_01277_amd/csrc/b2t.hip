@@ -1,0 +1,230 @@
+// Band -> tridiagonal reduction by bulge chasing (C ABI in
+// include/elpa_b2t.h; Kus et al., Sec. 2), one column per chase step, with
+// the reflectors written in the slot layout of the tridiagonal -> band
+// back-transformation.
+//
+// Schedule.  Chase step (s, j) (row r = s+1+j*nbw, length L <= nbw) reads and
+// writes only the square [r-nbw, r+L+nbw) x [r-nbw, r+L+nbw) of the matrix.
+// Step (s+1, j') overlaps a step (s, j'') only for j'' <= j'+3, and two steps
+// of one sweep overlap only when adjacent; so with the launch index
+//   t(s, j) = j + 4 s
+// every overlapping pair runs in launches ordered as in the sequential
+// reduction (sweep by sweep, step by step), and the steps of one launch
+// (same t, distinct s) touch disjoint squares.  One workgroup per step;
+// kernel boundaries order the launches.  There is no waiting between
+// workgroups.
+//
+// A step: the reflector from column c (= s for j = 0, else r - nbw), rows
+// [r, r+L) (LAPACK's larfg convention), then the left update of rows
+// [r, r+L) over the window's columns (one wave per column, lanes over rows)
+// and the right update of columns [r, r+L) over the window's rows (one
+// thread per row), then the eliminated entries written exactly.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/elpa_b2t.h"
+#include "../../include/elpa_hh.h"
+#include "hh_common.h"
+
+namespace eb2t {
+
+using ehh::z64;
+
+// scalar operations on double / complex double
+__device__ __forceinline__ double conj_(double a) { return a; }
+__device__ __forceinline__ z64 conj_(z64 a) { return z64{a.re, -a.im}; }
+__device__ __forceinline__ double mul(double a, double b) { return a * b; }
+__device__ __forceinline__ z64 mul(z64 a, z64 b) {
+  return z64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+__device__ __forceinline__ double add(double a, double b) { return a + b; }
+__device__ __forceinline__ z64 add(z64 a, z64 b) { return z64{a.re + b.re, a.im + b.im}; }
+__device__ __forceinline__ double sub(double a, double b) { return a - b; }
+__device__ __forceinline__ z64 sub(z64 a, z64 b) { return z64{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ double abs2(double a) { return a * a; }
+__device__ __forceinline__ double abs2(z64 a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ double re(double a) { return a; }
+__device__ __forceinline__ double re(z64 a) { return a.re; }
+__device__ __forceinline__ double im(double) { return 0.0; }
+__device__ __forceinline__ double im(z64 a) { return a.im; }
+template <typename E>
+__device__ __forceinline__ E from_re(double x) {
+  if constexpr (std::is_same<E, double>::value)
+    return x;
+  else
+    return z64{x, 0.0};
+}
+template <typename E>
+__device__ __forceinline__ E zero() {
+  return from_re<E>(0.0);
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) x += __shfl_xor(x, w, 64);
+  return x;
+}
+__device__ __forceinline__ z64 wave_sum(z64 x) { return z64{wave_sum(x.re), wave_sum(x.im)}; }
+
+constexpr int kMaxNb = 512;
+
+// one launch: the steps (s, t - 4 s) for s = s_lo .. s_lo + gridDim.x - 1
+template <typename E>
+__global__ __launch_bounds__(256) void k_chase(E* __restrict__ A, int64_t lda, int64_t n,
+                                               int64_t nb, int64_t t, int64_t s_lo,
+                                               E* __restrict__ hh, E* __restrict__ tau) {
+  __shared__ E v[kMaxNb];
+  __shared__ double part[4];
+  __shared__ E sh_tau;
+  __shared__ double sh_beta;
+  const int64_t s = s_lo + blockIdx.x;
+  const int64_t j = t - 4 * s;
+  const int64_t r = s + 1 + j * nb;
+  const int64_t L = (nb < n - r) ? nb : n - r;
+  const int64_t c = (j == 0) ? s : r - nb;
+  const int64_t lo = (r - nb > 0) ? r - nb : 0;
+  const int64_t hi = (r + L + nb < n) ? r + L + nb : n;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  auto at = [&](int64_t i, int64_t k) -> E& { return A[i + k * lda]; };
+
+  // reflector: x = A[r .. r+L, c]
+  double ss = 0.0;
+  for (int64_t i = tid; i < L; i += blockDim.x) {
+    const E x = at(r + i, c);
+    v[i] = x;
+    if (i >= 1) ss += abs2(x);
+  }
+  ss = wave_sum(ss);
+  if (lane == 0) part[wave] = ss;
+  __syncthreads();
+  if (tid == 0) {
+    const double sum = part[0] + part[1] + part[2] + part[3];
+    const E alpha = v[0];
+    const double ar = re(alpha), ai = im(alpha);
+    if (sum == 0.0 && ai == 0.0) {
+      sh_tau = zero<E>();
+      sh_beta = ar;
+      part[0] = 0.0;  // no scaling needed
+    } else {
+      const double h = sqrt(ar * ar + ai * ai + sum);
+      const double bt = (ar >= 0.0) ? -h : h;
+      if constexpr (std::is_same<E, double>::value)
+        sh_tau = (bt - ar) / bt;
+      else
+        sh_tau = z64{(bt - ar) / bt, -ai / bt};
+      sh_beta = bt;
+      part[0] = 1.0;
+    }
+  }
+  __syncthreads();
+  const E tv = sh_tau;
+  const bool act = part[0] != 0.0;
+  if (act) {
+    // scale 1 / (alpha - beta)
+    const E den = sub(v[0], from_re<E>(sh_beta));
+    E sc;
+    if constexpr (std::is_same<E, double>::value) {
+      sc = 1.0 / den;
+    } else {
+      const double dd = den.re * den.re + den.im * den.im;
+      sc = z64{den.re / dd, -den.im / dd};
+    }
+    __syncthreads();
+    for (int64_t i = 1 + tid; i < L; i += blockDim.x) v[i] = mul(v[i], sc);
+  }
+  __syncthreads();
+  if (tid == 0) v[0] = from_re<E>(1.0);
+  __syncthreads();
+
+  if (act) {
+    // left: rows [r, r+L) of columns [lo, hi) <- H^H rows, H^H = I - conj(tau) v v^H
+    const E ct = conj_(tv);
+    for (int64_t k = lo + wave; k < hi; k += 4) {
+      E acc = zero<E>();
+      for (int64_t i = lane; i < L; i += 64) acc = add(acc, mul(conj_(v[i]), at(r + i, k)));
+      const E w = mul(ct, wave_sum(acc));
+      for (int64_t i = lane; i < L; i += 64) at(r + i, k) = sub(at(r + i, k), mul(v[i], w));
+    }
+    __syncthreads();
+    // right: columns [r, r+L) of rows [lo, hi) <- cols H, H = I - tau v v^H
+    for (int64_t i = lo + tid; i < hi; i += blockDim.x) {
+      E acc = zero<E>();
+      for (int64_t q = 0; q < L; ++q) acc = add(acc, mul(at(i, r + q), v[q]));
+      const E w = mul(acc, tv);
+      for (int64_t q = 0; q < L; ++q) at(i, r + q) = sub(at(i, r + q), mul(w, conj_(v[q])));
+    }
+  }
+  __syncthreads();
+  // eliminated entries, the reflector in its slot
+  const E beta = from_re<E>(sh_beta);
+  const int64_t slot = ehh::slot_offset(n, nb, s) + j;
+  E* __restrict__ dst = hh + slot * nb;
+  for (int64_t i = tid; i < nb; i += blockDim.x) {
+    if (i < L) {
+      const E z = (i == 0) ? beta : zero<E>();
+      at(r + i, c) = z;
+      at(c, r + i) = z;
+    }
+    dst[i] = (i < L) ? v[i] : zero<E>();
+  }
+  if (tid == 0) tau[slot] = tv;
+}
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_diag_out(const E* __restrict__ A, int64_t lda,
+                                                  int64_t n, double* __restrict__ d,
+                                                  double* __restrict__ e) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    d[i] = re(A[i + i * lda]);
+    if (i + 1 < n) e[i] = re(A[i + 1 + i * lda]);
+  }
+}
+
+// J(s) = ceil((n-1-s)/nb)
+inline int64_t steps_of(int64_t n, int64_t nb, int64_t s) { return (n - 1 - s + nb - 1) / nb; }
+
+template <typename E>
+int run(int64_t n, int64_t nb, E* A, int64_t lda, double* d, double* e, E* hh, E* tau,
+        hipStream_t st) {
+  // launches t = 0 .. T-1 with T = max_s (4 s + J(s)); the active sweeps of
+  // launch t are s_lo(t) .. min(t / 4, n - 2), s_lo the least s with
+  // 4 s + J(s) > t (4 s + J(s) increases with s)
+  int64_t T = 0;
+  for (int64_t s = 0; s <= n - 2; ++s) T = std::max(T, 4 * s + steps_of(n, nb, s));
+  int64_t s_lo = 0;
+  for (int64_t t = 0; t < T; ++t) {
+    while (s_lo <= n - 2 && 4 * s_lo + steps_of(n, nb, s_lo) <= t) ++s_lo;
+    const int64_t s_hi = std::min<int64_t>(t / 4, n - 2);
+    if (s_hi < s_lo) continue;
+    hipLaunchKernelGGL(k_chase<E>, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, st, A, lda,
+                       n, nb, t, s_lo, hh, tau);
+  }
+  const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_diag_out<E>, dim3(g), dim3(256), 0, st, (const E*)A, lda, n, d, e);
+  return hipGetLastError() == hipSuccess ? ELPA_OK : ELPA_ERR_DEVICE;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace eb2t
+
+extern "C" int elpa_band_to_tridiag(int64_t n, int64_t nbw, void* A, int64_t lda, double* d,
+                                    double* e, void* hh, void* tau, int32_t dtype,
+                                    void* stream) {
+  if (dtype != ELPA_R64 && dtype != ELPA_C64) return ELPA_ERR_DTYPE;
+  if (n < 1 || nbw < 1 || nbw > eb2t::kMaxNb || lda < n) return ELPA_ERR_ARG;
+  if (!A || !d || (n > 1 && (!e || !hh || !tau))) return ELPA_ERR_ARG;
+  const size_t es = dtype == ELPA_C64 ? 16 : 8;
+  if (!eb2t::aligned(A, es) || !eb2t::aligned(d, 8) || (n > 1 && (!eb2t::aligned(e, 8) ||
+      !eb2t::aligned(hh, es) || !eb2t::aligned(tau, es))))
+    return ELPA_ERR_ALIGN;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (dtype == ELPA_R64)
+    return eb2t::run<double>(n, nbw, (double*)A, lda, d, e, (double*)hh, (double*)tau, st);
+  return eb2t::run<ehh::z64>(n, nbw, (ehh::z64*)A, lda, d, e, (ehh::z64*)hh, (ehh::z64*)tau,
+                             st);
+}

@@ -200,3 +200,16 @@ def test_bt2_argument_errors_and_workspace():
     al = lambda x: -(-x // 256) * 256
     assert P.bt2_workspace_bytes(100, 5, 32, P.R64, 64) == \
         al(68 * 64 * 8) + 2 * al(64 * 64 * 8) + al(64 * 5 * 8) + al(64 * 64 * 8)
+
+
+def test_band_to_tridiag_argument_errors():
+    """Bulge chasing: argument checks before anything touches a device."""
+    lib = P.library()
+    nul = None
+    assert lib.elpa_band_to_tridiag(10, 2, nul, 10, nul, nul, nul, nul, P.R32, nul) == -2
+    assert lib.elpa_band_to_tridiag(10, 2, nul, 10, nul, nul, nul, nul, 9, nul) == -2
+    assert lib.elpa_band_to_tridiag(0, 2, nul, 10, nul, nul, nul, nul, P.R64, nul) == -1
+    assert lib.elpa_band_to_tridiag(10, 0, nul, 10, nul, nul, nul, nul, P.R64, nul) == -1
+    assert lib.elpa_band_to_tridiag(10, 513, nul, 10, nul, nul, nul, nul, P.R64, nul) == -1
+    assert lib.elpa_band_to_tridiag(10, 2, nul, 9, nul, nul, nul, nul, P.R64, nul) == -1
+    assert lib.elpa_band_to_tridiag(10, 2, nul, 10, nul, nul, nul, nul, P.R64, nul) == -1

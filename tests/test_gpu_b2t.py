@@ -1,0 +1,136 @@
+"""GPU band -> tridiagonal reduction (include/elpa_b2t.h) against the oracle's
+band_to_tridiag, and the reflectors it leaves in device memory used as they
+are by the tridiagonal -> band back-transformation."""
+import numpy as np
+import pytest
+
+import workload as W
+from oracle import bt, checks, stage1, stage2, tridiag
+
+from bt2_layout import panels_to_abi
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import time
+    t0 = time.time()
+    print("importing torch", flush=True)
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1811_01277_amd as P
+    P.library()
+    print(f"torch ready after {time.time() - t0:.1f} s", flush=True)
+    return torch, torch.device("cuda:0")
+
+
+def band_matrix(n, b, cplx, seed):
+    """The first stage's band matrix of a Gaussian Hermitian matrix."""
+    A = W.herm_gaussian(n, seed) if cplx else W.sym_gaussian(n, seed)
+    B, _ = stage1.full_to_band(A, b)
+    return B
+
+
+def gpu_b2t(torch, dev, B, b):
+    import paper_1811_01277_amd as P
+    a = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev).t()
+    return P.band_to_tridiag(a, b)
+
+
+def rel(x, ref):
+    m = float(np.max(np.abs(ref))) if np.size(ref) else 0.0
+    return float(np.max(np.abs(np.asarray(x) - ref))) / (m if m else 1.0) if np.size(ref) else 0.0
+
+
+CASES = [(97, 32, 401), (130, 64, 402), (300, 32, 403), (40, 1, 404), (20, 19, 405),
+         (2, 1, 406), (64, 5, 407)]
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("case", CASES, ids=[f"n{c[0]}_b{c[1]}" for c in CASES])
+def test_b2t_matches_oracle(torch_dev, case, cplx):
+    torch, dev = torch_dev
+    n, b, seed = case
+    B = band_matrix(n, b, cplx, seed)
+    d0, e0, hh0, tau0 = stage2.band_to_tridiag(B, b)
+    print(f"b2t n={n} b={b} cplx={cplx}", flush=True)
+    d, e, hh, tau = gpu_b2t(torch, dev, B, b)
+    torch.cuda.synchronize()
+    d, e, hh, tau = (x.cpu().numpy() for x in (d, e, hh, tau))
+    scale = float(np.max(np.abs(B)))
+    assert np.max(np.abs(d - d0)) <= 1e-12 * scale * max(1, n) ** 0.5
+    assert np.max(np.abs(e - e0), initial=0.0) <= 1e-12 * scale * max(1, n) ** 0.5
+    assert rel(hh, hh0) <= 1e-10 and rel(tau, tau0) <= 1e-10
+    # same eigenvalues as the band matrix
+    lam = np.linalg.eigvalsh(B)
+    T = np.diag(d) + np.diag(e, -1) + np.diag(e, 1)
+    assert np.max(np.abs(np.linalg.eigvalsh(T) - lam)) <= 1e-12 * scale * n
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_device_reflectors_drive_back_transform(torch_dev, cplx):
+    """d, e from the GPU -> tridiagonal eigenvectors (oracle) -> elpa_hh_trafo
+    with the GPU's hh / tau, never copied to the host: the band eigenvectors
+    satisfy the residual and orthogonality invariants of B."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, b = 256, 32
+    B = band_matrix(n, b, cplx, 411)
+    d, e, hh, tau = gpu_b2t(torch, dev, B, b)
+    lam, Zt = tridiag.eigh_tridiag(d.cpu().numpy(), e.cpu().numpy())
+    dt = np.complex128 if cplx else np.float64
+    q = torch.from_numpy(np.ascontiguousarray(Zt.astype(dt).T)).to(dev).t()
+    P.hh_trafo(q, hh, tau, b)
+    torch.cuda.synchronize()
+    Zb = q.cpu().numpy()
+    assert checks.residual_ratio(B, Zb, lam) < 50
+    assert checks.orth_ratio(Zb) < 50
+    # the oracle's chain from its own reflectors gives the same vectors
+    d0, e0, hh0, tau0 = stage2.band_to_tridiag(B, b)
+    ref = bt.bt_tridiag_to_band(hh0, tau0, Zt.astype(dt), n, b)
+    assert checks.max_rel_err(Zb, ref) <= 1e-10
+
+
+def test_whole_eigenvector_chain(torch_dev):
+    """Full -> band (oracle), band -> tridiagonal (GPU), tridiagonal solve
+    (oracle), tridiagonal -> band and band -> full (GPU): A Z = Z Lambda."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, b = 300, 32
+    A = W.sym_gaussian(n, 421)
+    B, panels = stage1.full_to_band(A, b)
+    d, e, hh, tau = gpu_b2t(torch, dev, B, b)
+    lam, Zt = tridiag.eigh_tridiag(d.cpu().numpy(), e.cpu().numpy())
+    q = torch.from_numpy(np.ascontiguousarray(Zt.T)).to(dev).t()
+    P.hh_trafo(q, hh, tau, b)
+    V, t1 = panels_to_abi(panels, n, b, np.float64)
+    v = torch.from_numpy(np.ascontiguousarray(V.T)).to(dev).t()
+    P.bt2_trafo(q, v, torch.from_numpy(t1).to(dev), b)
+    torch.cuda.synchronize()
+    Z = q.cpu().numpy()
+    assert checks.residual_ratio(A, Z, lam) < 50
+    assert checks.orth_ratio(Z) < 50
+
+
+def test_b2t_n2000(torch_dev):
+    """n = 2000, nbw = 64 (about 32000 chase steps).  The tridiagonal matrix is
+    a forward result whose entries drift from the oracle's as rounding
+    differences accumulate over the steps (3e-10 relative here), so they get
+    a loose bound; its eigenvalues, which a backward-stable reduction keeps,
+    are held to eps-level against the band matrix's."""
+    torch, dev = torch_dev
+    n, b = 2000, 64
+    G = np.random.default_rng(431).standard_normal((n, n))
+    B = (G + G.T) / 2.0
+    B[np.abs(np.subtract.outer(np.arange(n), np.arange(n))) > b] = 0.0
+    d0, e0, hh0, tau0 = stage2.band_to_tridiag(B, b)
+    d, e, hh, tau = gpu_b2t(torch, dev, B, b)
+    torch.cuda.synchronize()
+    d, e = d.cpu().numpy(), e.cpu().numpy()
+    scale = float(np.max(np.abs(B)))
+    lam = np.linalg.eigvalsh(B)
+    lt = np.linalg.eigvalsh(np.diag(d) + np.diag(e, -1) + np.diag(e, 1))
+    assert np.max(np.abs(lt - lam)) <= 50 * n * np.finfo(float).eps * np.linalg.norm(B, 2)
+    assert np.max(np.abs(d - d0)) <= 1e-7 * scale and np.max(np.abs(e - e0)) <= 1e-7 * scale
+    assert rel(hh.cpu().numpy(), hh0) <= 1e-6 and rel(tau.cpu().numpy(), tau0) <= 1e-6

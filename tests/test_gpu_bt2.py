@@ -10,6 +10,8 @@ import pytest
 import workload as W
 from oracle import bt, checks, solve, stage1
 
+from bt2_layout import abi_to_panels, panels_to_abi
+
 pytestmark = pytest.mark.gpu
 
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
@@ -34,36 +36,6 @@ def npdtype(dt):
 
 def rounded(x, dt):
     return x.astype(np.float32).astype(np.float64) if dt == "r32" else x
-
-
-def panels_to_abi(panels, n, nbw, dtype):
-    """(V, tau) in the library layout from stage1.full_to_band's panels."""
-    N = max(0, n - nbw)
-    V = np.full((n, max(N, 1)), np.nan, dtype=dtype, order="F")
-    tau = np.zeros(max(N, 1), dtype=dtype)
-    for p, Vp, taus in panels:
-        for i in range(Vp.shape[1]):
-            c = p + i
-            V[c + nbw + 1:, c] = Vp[i + 1:, i]
-            tau[c] = taus[i]
-    return V, tau
-
-
-def abi_to_panels(V, tau, n, nbw):
-    """The oracle's panel format from the library layout (unit leads and
-    zeros written explicitly)."""
-    panels = []
-    p = 0
-    while p + nbw < n:
-        m = n - p - nbw
-        k = min(nbw, m)
-        Vp = np.zeros((m, k), dtype=V.dtype)
-        for i in range(k):
-            Vp[i, i] = 1.0
-            Vp[i + 1:, i] = V[p + nbw + i + 1:, p + i]
-        panels.append((p, Vp, tau[p:p + k].copy()))
-        p += nbw
-    return panels
 
 
 def to_dev(torch, dev, a, dt, ld=None):
