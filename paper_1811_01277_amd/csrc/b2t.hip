@@ -18,7 +18,9 @@
 // [r, r+L) (LAPACK's larfg convention), then the left update of rows
 // [r, r+L) over the window's columns (one wave per column, lanes over rows)
 // and the right update of columns [r, r+L) over the window's rows (one
-// thread per row), then the eliminated entries written exactly.
+// thread per row), then the eliminated entries written exactly.  The step is
+// bound by memory latency, so both updates issue a chunk of independent
+// loads before using any of them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -71,13 +73,14 @@ __device__ __forceinline__ z64 wave_sum(z64 x) { return z64{wave_sum(x.re), wave
 
 constexpr int kMaxNb = 512;
 
-// one launch: the steps (s, t - 4 s) for s = s_lo .. s_lo + gridDim.x - 1
+// one launch: the steps (s, t - 4 s) for s = s_lo .. s_lo + gridDim.x - 1, one
+// 512-thread workgroup (8 waves) per step
 template <typename E>
-__global__ __launch_bounds__(256) void k_chase(E* __restrict__ A, int64_t lda, int64_t n,
+__global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, int64_t n,
                                                int64_t nb, int64_t t, int64_t s_lo,
                                                E* __restrict__ hh, E* __restrict__ tau) {
   __shared__ E v[kMaxNb];
-  __shared__ double part[4];
+  __shared__ double part[8];
   __shared__ E sh_tau;
   __shared__ double sh_beta;
   const int64_t s = s_lo + blockIdx.x;
@@ -101,7 +104,8 @@ __global__ __launch_bounds__(256) void k_chase(E* __restrict__ A, int64_t lda, i
   if (lane == 0) part[wave] = ss;
   __syncthreads();
   if (tid == 0) {
-    const double sum = part[0] + part[1] + part[2] + part[3];
+    double sum = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) sum += part[w];
     const E alpha = v[0];
     const double ar = re(alpha), ai = im(alpha);
     if (sum == 0.0 && ai == 0.0) {
@@ -140,21 +144,85 @@ __global__ __launch_bounds__(256) void k_chase(E* __restrict__ A, int64_t lda, i
   __syncthreads();
 
   if (act) {
-    // left: rows [r, r+L) of columns [lo, hi) <- H^H rows, H^H = I - conj(tau) v v^H
+    // left: rows [r, r+L) of columns [lo, hi) <- H^H rows, H^H = I - conj(tau) v v^H.
+    // A wave takes columns lo+wave, lo+wave+NW, ...; with L <= 64 a lane holds
+    // one row, and the values of CH columns are loaded before any is used,
+    // so CH loads are in flight at once.
     const E ct = conj_(tv);
-    for (int64_t k = lo + wave; k < hi; k += 4) {
-      E acc = zero<E>();
-      for (int64_t i = lane; i < L; i += 64) acc = add(acc, mul(conj_(v[i]), at(r + i, k)));
-      const E w = mul(ct, wave_sum(acc));
-      for (int64_t i = lane; i < L; i += 64) at(r + i, k) = sub(at(r + i, k), mul(v[i], w));
+    const int NW = (int)(blockDim.x >> 6);
+    if (L <= 64) {
+      constexpr int CH = 8;
+      const E vl = lane < L ? v[lane] : zero<E>();
+      const E cvl = conj_(vl);
+      for (int64_t k0 = lo + wave; k0 < hi; k0 += (int64_t)NW * CH) {
+        E x[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int64_t k = k0 + (int64_t)NW * u;
+          x[u] = (k < hi && lane < L) ? at(r + lane, k) : zero<E>();
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int64_t k = k0 + (int64_t)NW * u;
+          const E w = mul(ct, wave_sum(mul(cvl, x[u])));
+          if (k < hi && lane < L) at(r + lane, k) = sub(x[u], mul(vl, w));
+        }
+      }
+    } else {
+      for (int64_t k = lo + wave; k < hi; k += NW) {
+        E acc = zero<E>();
+        for (int64_t i = lane; i < L; i += 64) acc = add(acc, mul(conj_(v[i]), at(r + i, k)));
+        const E w = mul(ct, wave_sum(acc));
+        for (int64_t i = lane; i < L; i += 64) at(r + i, k) = sub(at(r + i, k), mul(v[i], w));
+      }
     }
     __syncthreads();
-    // right: columns [r, r+L) of rows [lo, hi) <- cols H, H = I - tau v v^H
-    for (int64_t i = lo + tid; i < hi; i += blockDim.x) {
+    // right: columns [r, r+L) of rows [lo, hi) <- cols H, H = I - tau v v^H.
+    // Four adjacent threads per row, each with QC consecutive columns of every
+    // 4 QC; their partial products are combined by lane shuffles (all four get
+    // the same sum in the same order), and every thread updates the values it
+    // loaded.  Rows with L > 4 QC reload their values for the update.
+    constexpr int QC = 16;
+    const int part4 = tid & 3;
+    const int64_t rows_per_pass = blockDim.x >> 2;
+    for (int64_t i0 = lo; i0 < hi; i0 += rows_per_pass) {
+      const int64_t i = i0 + (tid >> 2);
+      const bool row_ok = i < hi;
+      E y[QC];
       E acc = zero<E>();
-      for (int64_t q = 0; q < L; ++q) acc = add(acc, mul(at(i, r + q), v[q]));
-      const E w = mul(acc, tv);
-      for (int64_t q = 0; q < L; ++q) at(i, r + q) = sub(at(i, r + q), mul(w, conj_(v[q])));
+      for (int64_t q0 = 0; q0 < L; q0 += 4 * QC) {
+        const int64_t qb = q0 + (int64_t)part4 * QC;
+#pragma unroll
+        for (int u = 0; u < QC; ++u)
+          y[u] = (row_ok && qb + u < L) ? at(i, r + qb + u) : zero<E>();
+#pragma unroll
+        for (int u = 0; u < QC; ++u)
+          if (qb + u < L) acc = add(acc, mul(y[u], v[qb + u]));
+      }
+      // sum over the four threads of the row (lanes 4m .. 4m+3 of one wave)
+      E tot = acc;
+      if constexpr (std::is_same<E, double>::value) {
+        tot = tot + __shfl_xor(tot, 1, 64);
+        tot = tot + __shfl_xor(tot, 2, 64);
+      } else {
+        tot = z64{tot.re + __shfl_xor(tot.re, 1, 64), tot.im + __shfl_xor(tot.im, 1, 64)};
+        tot = z64{tot.re + __shfl_xor(tot.re, 2, 64), tot.im + __shfl_xor(tot.im, 2, 64)};
+      }
+      const E w = mul(tot, tv);
+      if (L <= 4 * QC) {
+        const int64_t qb = (int64_t)part4 * QC;
+#pragma unroll
+        for (int u = 0; u < QC; ++u)
+          if (row_ok && qb + u < L) at(i, r + qb + u) = sub(y[u], mul(w, conj_(v[qb + u])));
+      } else {
+        for (int64_t q0 = 0; q0 < L; q0 += 4 * QC) {
+          const int64_t qb = q0 + (int64_t)part4 * QC;
+#pragma unroll
+          for (int u = 0; u < QC; ++u)
+            if (row_ok && qb + u < L)
+              at(i, r + qb + u) = sub(at(i, r + qb + u), mul(w, conj_(v[qb + u])));
+        }
+      }
     }
   }
   __syncthreads();
@@ -200,7 +268,7 @@ int run(int64_t n, int64_t nb, E* A, int64_t lda, double* d, double* e, E* hh, E
     while (s_lo <= n - 2 && 4 * s_lo + steps_of(n, nb, s_lo) <= t) ++s_lo;
     const int64_t s_hi = std::min<int64_t>(t / 4, n - 2);
     if (s_hi < s_lo) continue;
-    hipLaunchKernelGGL(k_chase<E>, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, st, A, lda,
+    hipLaunchKernelGGL(k_chase<E>, dim3((unsigned)(s_hi - s_lo + 1)), dim3(512), 0, st, A, lda,
                        n, nb, t, s_lo, hh, tau);
   }
   const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
