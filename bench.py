@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload leg")
     ap.add_argument("--no-bt2", action="store_true",
                     help="skip the band->full back-transformation leg")
+    ap.add_argument("--no-b2t", action="store_true",
+                    help="skip the band->tridiagonal reduction leg")
     ap.add_argument("--bt2-only", action="store_true",
                     help="instead of the benchmark: only the band->full leg at --nev "
                          "(for profiling it on its own)")
@@ -212,6 +214,42 @@ def bt2_leg(args, nevs=None):
         del q
         torch.cuda.empty_cache()
     return out
+
+
+def b2t_leg(args):
+    """Band -> tridiagonal reduction (elpa_band_to_tridiag) on a random
+    symmetric band matrix of the same n, nbw 64, real fp64, drawn on the
+    device.  Latency-bound (about 4 n launches of independent chase steps), so
+    the figures are time, chase steps per second and time per launch."""
+    import torch
+    import paper_1811_01277_amd as P
+    dev = torch.device("cuda:0")
+    n, b = args.n, 64
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + 9)
+    G = torch.randn(n, n, device=dev, dtype=torch.float64, generator=g)
+    B = (G + G.t()) * 0.5
+    del G
+    i = torch.arange(n, device=dev)
+    B.masked_fill_((i[:, None] - i[None, :]).abs() > b, 0.0)
+    steps = P.num_reflectors(n, b)
+    launches = max(4 * s + -(-(n - 1 - s) // b) for s in range(n - 1))
+    times = []
+    for _ in range(2):
+        a = B.clone().t()   # symmetric: the column-major view holds the same matrix
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        P.band_to_tridiag(a, b)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        del a
+    del B
+    torch.cuda.empty_cache()
+    t = min(times)
+    return {"workload": f"band->tridiagonal reduction, n={n}, nbw={b}, r64, random band "
+                        f"matrix", "s": round(t, 3), "chase_steps": steps,
+            "steps_per_s": round(steps / t), "launches": launches,
+            "us_per_launch": round(t / launches * 1e6, 2)}
 
 
 def recorded_traffic(workload):
@@ -412,6 +450,9 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_bt2:
         out["bt2"] = bt2_leg(args)
+        torch.cuda.empty_cache()
+    if not args.no_b2t:
+        out["b2t"] = b2t_leg(args)
         torch.cuda.empty_cache()
     if not args.no_served:
         out["served_stream"] = served_stream(args)
