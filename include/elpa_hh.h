@@ -267,6 +267,52 @@ void elpa_hh_tuner_clear(void);
 int elpa_hh_tuner_save(const char *path);
 int elpa_hh_tuner_load(const char *path);
 
+/*
+ * On-the-fly autotuning over a sequence of similar solves (Kus et al.,
+ * Sec. 4.3: an SCF cycle solves many similar problems, so every solve can try
+ * one candidate setting and the best one is kept for the rest).
+ *
+ * elpa_hh_autotune_setup: candidates for problems of this (n, nev, nbw,
+ *   dtype): ELPA_AUTOTUNE_FAST = the kernel family only (each family's
+ *   default k); ELPA_AUTOTUNE_MEDIUM = also the blocking parameters of the
+ *   back-transformation (every compiled k, chase steps per tile 0/2/4/8/16,
+ *   1 or 2 stripe-group streams).  `fixed` (may be NULL): its nonzero path,
+ *   k, steps and streams fields are kept at that value and excluded from the
+ *   search.  Returns NULL for invalid arguments or if no candidate can run.
+ *   The state's two HIP events are created on the device current at its
+ *   first step.
+ * elpa_hh_autotune_step: one solve of the sequence, i.e. elpa_hh_trafo_plan
+ *   on these arguments with the next candidate (the first step of a fresh
+ *   state runs the first candidate untimed, as a warm-up), timed with events
+ *   on `stream`; *tuning = 1 while candidates remain, 0 once every candidate
+ *   has been timed (the call then runs the fastest).  The result of every
+ *   step is the back-transformation itself, whichever candidate ran.  The
+ *   timing of a step is read at the next step (or by _best / _save), so a
+ *   step does not wait for the GPU.  Errors as elpa_hh_trafo_plan.
+ * elpa_hh_autotune_best: the fastest timed candidate so far (waits for a
+ *   pending timing); ELPA_ERR_ARG if none is timed yet.
+ * elpa_hh_autotune_set_best: stores it in the plan cache for this size
+ *   class (elpa_hh_tuner_set), so calls without a plan use it.
+ * elpa_hh_autotune_save / _load: the state as text ("elpa_hh_autotune 1",
+ *   the problem, the next candidate, then one line per candidate with its
+ *   time or -1), so tuning can stop and resume in a later run; _load returns
+ *   NULL for a file that does not parse.
+ * elpa_hh_autotune_free: releases the state and its events.
+ */
+enum { ELPA_AUTOTUNE_FAST = 0, ELPA_AUTOTUNE_MEDIUM = 1 };
+typedef struct elpa_hh_autotune_state elpa_hh_autotune_state;
+elpa_hh_autotune_state *elpa_hh_autotune_setup(int32_t level, int64_t n, int64_t nev,
+                                               int64_t nbw, int32_t dtype,
+                                               const elpa_hh_plan *fixed);
+int elpa_hh_autotune_step(elpa_hh_autotune_state *st, const void *hh, const void *tau,
+                          void *Q, int64_t ldq, void *stream, int32_t *tuning);
+int elpa_hh_autotune_best(elpa_hh_autotune_state *st, elpa_hh_plan *best);
+int elpa_hh_autotune_set_best(elpa_hh_autotune_state *st);
+int elpa_hh_autotune_save(elpa_hh_autotune_state *st, const char *path);
+elpa_hh_autotune_state *elpa_hh_autotune_load(const char *path);
+int64_t elpa_hh_autotune_candidates(const elpa_hh_autotune_state *st);
+void elpa_hh_autotune_free(elpa_hh_autotune_state *st);
+
 /* Static message for a return code (never NULL). */
 const char *elpa_strerror(int code);
 

@@ -9,6 +9,7 @@ There is no CPU fallback: if the library is missing, import of the binding
 functions raises.
 """
 from .binding import (  # noqa: F401
+    AUTOTUNE_FAST, AUTOTUNE_MEDIUM, Autotune,
     C64, ORDER_AUTO, ORDER_LINEAR, ORDER_XCD, PATH_AUTO, PATH_REF, PATH_SPLIT, PATH_STRIPE, PATH_WY,
     R32, R64, ElpaError, band_to_tridiag, bt2_trafo, bt2_workspace_bytes, hh_trafo,
     hh_trafo_batched, hh_trafo_ptr, library, library_path, num_reflectors, plan_supported,

@@ -67,6 +67,22 @@ def library():
         L.elpa_hh_workspace_bytes_batched.restype = i64
         L.elpa_hh_tune.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, i32, C.POINTER(_Plan)]
         L.elpa_hh_tune.restype = C.c_int
+        L.elpa_hh_autotune_setup.argtypes = [i32, i64, i64, i64, i32, C.POINTER(_Plan)]
+        L.elpa_hh_autotune_setup.restype = p
+        L.elpa_hh_autotune_step.argtypes = [p, p, p, p, i64, p, C.POINTER(i32)]
+        L.elpa_hh_autotune_step.restype = C.c_int
+        L.elpa_hh_autotune_best.argtypes = [p, C.POINTER(_Plan)]
+        L.elpa_hh_autotune_best.restype = C.c_int
+        L.elpa_hh_autotune_set_best.argtypes = [p]
+        L.elpa_hh_autotune_set_best.restype = C.c_int
+        L.elpa_hh_autotune_save.argtypes = [p, C.c_char_p]
+        L.elpa_hh_autotune_save.restype = C.c_int
+        L.elpa_hh_autotune_load.argtypes = [C.c_char_p]
+        L.elpa_hh_autotune_load.restype = p
+        L.elpa_hh_autotune_candidates.argtypes = [p]
+        L.elpa_hh_autotune_candidates.restype = i64
+        L.elpa_hh_autotune_free.argtypes = [p]
+        L.elpa_hh_autotune_free.restype = None
         L.elpa_band_to_tridiag.argtypes = [i64, i64, p, i64, p, p, p, p, i32, p]
         L.elpa_band_to_tridiag.restype = C.c_int
         L.elpa_bt2_trafo.argtypes = [i64, i64, i64, p, i64, p, p, i64, i32, p, i64]
@@ -417,3 +433,78 @@ def band_to_tridiag(a, nbw, stream=None):
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
     return d, e[:max(n - 1, 0)], hh[:nr * nbw], tau[:nr]
+
+
+AUTOTUNE_FAST, AUTOTUNE_MEDIUM = 0, 1
+
+
+class Autotune:
+    """On-the-fly autotuning over a sequence of similar solves
+    (elpa_hh_autotune_* in include/elpa_hh.h): every step() is one real
+    back-transformation with the next candidate setting; once all have been
+    timed, steps run the fastest.
+
+        at = Autotune(AUTOTUNE_MEDIUM, n, nev, nbw, R64)
+        for each SCF step:  tuning = at.step(q, hh, tau)
+        at.set_best()   # plain hh_trafo calls of this size class use it
+    """
+
+    def __init__(self, level, n, nev, nbw, dtype, path=0, k=0, steps=0, streams=0, _state=None):
+        if _state is not None:
+            self._st = _state
+        else:
+            fixed = _plan(path or None, k, steps, 0, streams)
+            self._st = library().elpa_hh_autotune_setup(
+                level, n, nev, nbw, dtype, C.byref(fixed) if fixed is not None else None)
+            if not self._st:
+                raise ElpaError(-1, "autotune setup refused (arguments or no candidate)")
+
+    @classmethod
+    def load(cls, path):
+        st = library().elpa_hh_autotune_load(os.fsencode(path))
+        if not st:
+            raise ElpaError(-1, "autotune state file does not parse")
+        return cls(0, 0, 0, 0, 0, _state=st)
+
+    @property
+    def candidates(self):
+        return int(library().elpa_hh_autotune_candidates(self._st))
+
+    def step(self, q, hh, tau, stream=None):
+        """One solve (Q <- H ... H Q in place); returns True while tuning."""
+        import torch
+        n, nev = q.shape
+        ldq = q.stride(1) if nev > 1 else max(n, 1)
+        if stream is None:
+            st = torch.cuda.current_stream(q.device).cuda_stream
+        elif isinstance(stream, int):
+            st = stream
+        else:
+            st = stream.cuda_stream
+        tuning = C.c_int32(0)
+        _check(library().elpa_hh_autotune_step(
+            self._st, C.c_void_p(hh.data_ptr()), C.c_void_p(tau.data_ptr()),
+            C.c_void_p(q.data_ptr()), ldq, C.c_void_p(st), C.byref(tuning)))
+        return bool(tuning.value)
+
+    def best(self):
+        out = _Plan()
+        _check(library().elpa_hh_autotune_best(self._st, C.byref(out)))
+        return _plan_dict(out)
+
+    def set_best(self):
+        _check(library().elpa_hh_autotune_set_best(self._st))
+
+    def save(self, path):
+        _check(library().elpa_hh_autotune_save(self._st, os.fsencode(path)))
+
+    def close(self):
+        if getattr(self, "_st", None):
+            library().elpa_hh_autotune_free(self._st)
+            self._st = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

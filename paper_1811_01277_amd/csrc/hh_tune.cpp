@@ -307,3 +307,230 @@ int elpa_hh_tune_batched(const elpa_hh_problem* probs, int64_t count, void* stre
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// On-the-fly autotuning over a sequence of solves (C ABI in include/elpa_hh.h)
+// ---------------------------------------------------------------------------
+struct elpa_hh_autotune_state {
+  int32_t level = 0, dtype = 0;
+  int64_t n = 0, nev = 0, nbw = 0;
+  std::vector<elpa_hh_plan> cand;
+  std::vector<double> ms;  // -1: not timed
+  int64_t next = -1;       // -1: warm-up step pending
+  int64_t pending = -1;    // candidate whose events are not read yet
+  hipEvent_t a = nullptr, b = nullptr;
+};
+
+namespace ehh {
+namespace {
+
+std::vector<elpa_hh_plan> autotune_candidates(int32_t level, int64_t nbw, int32_t dtype,
+                                              const elpa_hh_plan* fixed) {
+  std::vector<elpa_hh_plan> out;
+  const elpa_hh_plan fx = fixed ? *fixed : elpa_hh_plan{0, 0, 0, 0, 0, 0};
+  const int steps_all[] = {0, 2, 4, 8, 16};
+  for (int fam : {ELPA_PATH_SPLIT, ELPA_PATH_WY, ELPA_PATH_STRIPE}) {
+    if (fx.path && fx.path != fam) continue;
+    std::vector<int> ks;
+    if (fx.k) {
+      ks.push_back(fx.k);
+    } else if (level == ELPA_AUTOTUNE_FAST) {
+      ks.push_back(0);
+    } else {
+      int cnt = 0;
+      const StripeEntry* tab = fam == ELPA_PATH_SPLIT ? split_table(&cnt)
+                               : fam == ELPA_PATH_WY  ? wy_table(&cnt)
+                                                      : stripe_table(&cnt);
+      for (int i = 0; i < cnt; ++i)
+        if (tab[i].dtype == dtype && tab[i].nb == nbw) ks.push_back(tab[i].k);
+    }
+    std::vector<int> steps, streams;
+    if (fx.steps)
+      steps.push_back(fx.steps);
+    else if (level == ELPA_AUTOTUNE_FAST)
+      steps.push_back(0);
+    else
+      steps.assign(std::begin(steps_all), std::end(steps_all));
+    if (fx.streams)
+      streams.push_back(fx.streams);
+    else if (level == ELPA_AUTOTUNE_FAST)
+      streams.push_back(0);
+    else
+      streams = {1, 2};
+    for (int k : ks)
+      for (int s : steps)
+        for (int ns : streams) {
+          const elpa_hh_plan p{fam, k, s, fx.order, ns, 0};
+          if (elpa_hh_plan_supported(nbw, dtype, &p)) out.push_back(p);
+        }
+  }
+  return out;
+}
+
+// read the pending timing (waits for the step's end event)
+int autotune_settle(elpa_hh_autotune_state* st) {
+  if (st->pending < 0) return ELPA_OK;
+  float ms = 0.f;
+  if (hipEventSynchronize(st->b) != hipSuccess ||
+      hipEventElapsedTime(&ms, st->a, st->b) != hipSuccess)
+    return ELPA_ERR_DEVICE;
+  st->ms[(size_t)st->pending] = ms;
+  st->pending = -1;
+  return ELPA_OK;
+}
+
+int64_t autotune_best_index(const elpa_hh_autotune_state* st) {
+  int64_t best = -1;
+  for (size_t i = 0; i < st->ms.size(); ++i)
+    if (st->ms[i] >= 0.0 && (best < 0 || st->ms[i] < st->ms[(size_t)best])) best = (int64_t)i;
+  return best;
+}
+
+bool autotune_events(elpa_hh_autotune_state* st) {
+  return hipEventCreate(&st->a) == hipSuccess && hipEventCreate(&st->b) == hipSuccess;
+}
+
+}  // namespace
+}  // namespace ehh
+
+extern "C" {
+
+elpa_hh_autotune_state* elpa_hh_autotune_setup(int32_t level, int64_t n, int64_t nev,
+                                               int64_t nbw, int32_t dtype,
+                                               const elpa_hh_plan* fixed) {
+  if (level != ELPA_AUTOTUNE_FAST && level != ELPA_AUTOTUNE_MEDIUM) return nullptr;
+  if (n <= 1 || nev <= 0 || nbw < 1) return nullptr;
+  if (dtype != ELPA_R64 && dtype != ELPA_R32 && dtype != ELPA_C64) return nullptr;
+  if (fixed && (fixed->k < 0 || fixed->steps < 0 || fixed->streams < 0 || fixed->streams > 8 ||
+                fixed->reserved != 0))
+    return nullptr;
+  auto* st = new elpa_hh_autotune_state();
+  st->level = level;
+  st->dtype = dtype;
+  st->n = n;
+  st->nev = nev;
+  st->nbw = nbw;
+  st->cand = ehh::autotune_candidates(level, nbw, dtype, fixed);
+  st->ms.assign(st->cand.size(), -1.0);
+  if (st->cand.empty()) {
+    elpa_hh_autotune_free(st);
+    return nullptr;
+  }
+  return st;
+}
+
+int64_t elpa_hh_autotune_candidates(const elpa_hh_autotune_state* st) {
+  return st ? (int64_t)st->cand.size() : -1;
+}
+
+int elpa_hh_autotune_step(elpa_hh_autotune_state* st, const void* hh, const void* tau, void* Q,
+                          int64_t ldq, void* stream, int32_t* tuning) {
+  if (!st || !tuning) return ELPA_ERR_ARG;
+  // the events belong to the device current at the first step
+  if (!st->a && !ehh::autotune_events(st)) return ELPA_ERR_DEVICE;
+  int rc = ehh::autotune_settle(st);
+  if (rc != ELPA_OK) return rc;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (st->next < 0) {  // warm-up: the first candidate, untimed
+    rc = elpa_hh_trafo_plan(st->n, st->nev, st->nbw, hh, tau, Q, ldq, st->dtype, stream,
+                            &st->cand[0]);
+    if (rc == ELPA_OK) st->next = 0;
+    *tuning = 1;
+    return rc;
+  }
+  if (st->next < (int64_t)st->cand.size()) {
+    const int64_t i = st->next;
+    if (hipEventRecord(st->a, s) != hipSuccess) return ELPA_ERR_DEVICE;
+    rc = elpa_hh_trafo_plan(st->n, st->nev, st->nbw, hh, tau, Q, ldq, st->dtype, stream,
+                            &st->cand[(size_t)i]);
+    if (rc != ELPA_OK) return rc;
+    if (hipEventRecord(st->b, s) != hipSuccess) return ELPA_ERR_DEVICE;
+    st->pending = i;
+    st->next = i + 1;
+    *tuning = st->next < (int64_t)st->cand.size() ? 1 : 0;
+    return ELPA_OK;
+  }
+  *tuning = 0;
+  const int64_t b = ehh::autotune_best_index(st);
+  return elpa_hh_trafo_plan(st->n, st->nev, st->nbw, hh, tau, Q, ldq, st->dtype, stream,
+                            &st->cand[(size_t)(b < 0 ? 0 : b)]);
+}
+
+int elpa_hh_autotune_best(elpa_hh_autotune_state* st, elpa_hh_plan* best) {
+  if (!st || !best) return ELPA_ERR_ARG;
+  const int rc = ehh::autotune_settle(st);
+  if (rc != ELPA_OK) return rc;
+  const int64_t b = ehh::autotune_best_index(st);
+  if (b < 0) return ELPA_ERR_ARG;
+  *best = st->cand[(size_t)b];
+  return ELPA_OK;
+}
+
+int elpa_hh_autotune_set_best(elpa_hh_autotune_state* st) {
+  elpa_hh_plan best{};
+  const int rc = elpa_hh_autotune_best(st, &best);
+  if (rc != ELPA_OK) return rc;
+  return elpa_hh_tuner_set(st->dtype, st->nbw, st->n, st->nev, &best);
+}
+
+int elpa_hh_autotune_save(elpa_hh_autotune_state* st, const char* path) {
+  if (!st || !path) return ELPA_ERR_ARG;
+  const int rc = ehh::autotune_settle(st);
+  if (rc != ELPA_OK) return rc;
+  FILE* f = std::fopen(path, "w");
+  if (!f) return ELPA_ERR_ARG;
+  std::fprintf(f, "elpa_hh_autotune 1\n");
+  std::fprintf(f, "%d %d %lld %lld %lld %lld %lld\n", st->level, st->dtype, (long long)st->n,
+               (long long)st->nev, (long long)st->nbw, (long long)st->next,
+               (long long)st->cand.size());
+  for (size_t i = 0; i < st->cand.size(); ++i) {
+    const elpa_hh_plan& p = st->cand[i];
+    std::fprintf(f, "%d %d %d %d %d %.6f\n", p.path, p.k, p.steps, p.order, p.streams,
+                 st->ms[i]);
+  }
+  return std::fclose(f) == 0 ? ELPA_OK : ELPA_ERR_ARG;
+}
+
+elpa_hh_autotune_state* elpa_hh_autotune_load(const char* path) {
+  if (!path) return nullptr;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return nullptr;
+  char line[512];
+  auto* st = new elpa_hh_autotune_state();
+  long long n = 0, nev = 0, nbw = 0, next = 0, cnt = 0;
+  bool ok = std::fgets(line, sizeof line, f) && std::strncmp(line, "elpa_hh_autotune 1", 18) == 0;
+  ok = ok && std::fgets(line, sizeof line, f) &&
+       std::sscanf(line, "%d %d %lld %lld %lld %lld %lld", &st->level, &st->dtype, &n, &nev, &nbw,
+                   &next, &cnt) == 7;
+  ok = ok && n > 1 && nev > 0 && nbw > 0 && cnt > 0 && cnt < 100000 && next >= -1 && next <= cnt;
+  for (long long i = 0; ok && i < cnt; ++i) {
+    elpa_hh_plan p{};
+    double ms = -1.0;
+    ok = std::fgets(line, sizeof line, f) &&
+         std::sscanf(line, "%d %d %d %d %d %lf", &p.path, &p.k, &p.steps, &p.order, &p.streams,
+                     &ms) == 6 &&
+         elpa_hh_plan_supported(nbw, st->dtype, &p);
+    st->cand.push_back(p);
+    st->ms.push_back(ms);
+  }
+  std::fclose(f);
+  st->n = n;
+  st->nev = nev;
+  st->nbw = nbw;
+  st->next = next;
+  if (!ok) {
+    elpa_hh_autotune_free(st);
+    return nullptr;
+  }
+  return st;
+}
+
+void elpa_hh_autotune_free(elpa_hh_autotune_state* st) {
+  if (!st) return;
+  if (st->pending >= 0 && st->b) (void)hipEventSynchronize(st->b);
+  if (st->a) (void)hipEventDestroy(st->a);
+  if (st->b) (void)hipEventDestroy(st->b);
+  delete st;
+}
+
+}  // extern "C"

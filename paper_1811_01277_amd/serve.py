@@ -5,7 +5,7 @@ A request is one tridiagonal->band back-transformation Q <- H ... H Q of a
 problem whose Q, reflectors and tau are resident on the device.  An SCF cycle
 solves a series of eigenproblems of one size whose matrix changes only
 slightly from step to step, in single or double precision (Kus et al.,
-Sec. 5): a sequence keeps its buffers across its consecutive solves, and the
+Sec. 5.1 and 5.2): a sequence keeps its buffers across its consecutive solves, and the
 upstream stages that refill them are not part of the timed service.
 
 Scheduling (all of it host logic around the C ABI; every step of the

@@ -122,3 +122,46 @@ def test_tune_batched_keeps_q_and_plan_runs(torch_dev):
         assert torch.equal(q, s), n
         ref = bt.bt_tridiag_to_band(hh, tau, Z, n, 32)
         assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12, n
+
+
+def test_autotune_over_a_solve_sequence(torch_dev, tmp_path):
+    """SCF-like sequence: every step is a correct back-transformation whichever
+    candidate runs; tuning ends after the warm-up and one step per candidate;
+    the state can be saved, reloaded and finished; set_best puts the winner in
+    the plan cache."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 600, 64, 200
+    q, h, t, (hh, tau, Z) = make(torch, dev, n, nbw, nev, 1400)
+    ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
+    zq = q.clone()
+    at = P.Autotune(P.AUTOTUNE_MEDIUM, n, nev, nbw, P.R64, path=P.PATH_SPLIT, k=64)
+    cands = at.candidates
+    assert cands == 10
+    steps, tuning = 0, True
+    while tuning and steps < 4:
+        q.copy_(zq)
+        tuning = at.step(q, h, t)
+        torch.cuda.synchronize()
+        assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12, steps
+        steps += 1
+    f = tmp_path / "at.txt"
+    at.save(str(f))
+    at.close()
+    at = P.Autotune.load(str(f))
+    while tuning:
+        q.copy_(zq)
+        tuning = at.step(q, h, t)
+        torch.cuda.synchronize()
+        assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12, steps
+        steps += 1
+        assert steps <= cands + 1
+    assert steps == cands + 1                         # warm-up + one per candidate
+    best = at.best()
+    assert best["path"] == P.PATH_SPLIT and best["k"] == 64
+    at.set_best()
+    assert P.tuner_get(P.R64, nbw, n, nev) == best
+    q.copy_(zq)
+    assert not at.step(q, h, t)                       # runs the best from now on
+    torch.cuda.synchronize()
+    assert checks.max_rel_err(q.cpu().numpy(), ref) <= 1e-12

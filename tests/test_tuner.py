@@ -105,3 +105,33 @@ def test_tune_batched_argument_errors():
     assert B.library().elpa_hh_tune_batched(arr, 1, None, 0, C.byref(out)) == -1   # ldq < n
     arr[0] = B._Problem(100, 10, 32, 100, None, None, None, 7, 0)
     assert B.library().elpa_hh_tune_batched(arr, 1, None, 0, C.byref(out)) == -2   # dtype
+
+
+def test_autotune_setup_levels_fixed_and_state_round_trip(tmp_path):
+    """On-the-fly autotuning state (no device call is made here)."""
+    fast = P.Autotune(P.AUTOTUNE_FAST, 20000, 20000, 64, P.R64)
+    med = P.Autotune(P.AUTOTUNE_MEDIUM, 20000, 20000, 64, P.R64)
+    split = P.Autotune(P.AUTOTUNE_MEDIUM, 20000, 20000, 64, P.R64, path=P.PATH_SPLIT)
+    k80 = P.Autotune(P.AUTOTUNE_MEDIUM, 20000, 20000, 64, P.R64, path=P.PATH_SPLIT, k=80)
+    # FAST: one candidate per kernel family; MEDIUM: also k, tile height, streams
+    assert fast.candidates == 3
+    assert med.candidates > split.candidates > k80.candidates == 10
+    f = tmp_path / "state.txt"
+    split.save(str(f))
+    text = f.read_text().splitlines()
+    assert text[0] == "elpa_hh_autotune 1" and len(text) == 2 + split.candidates
+    assert all(line.split()[0] == "3" for line in text[2:])      # the fixed family only
+    back = P.Autotune.load(str(f))
+    g = tmp_path / "again.txt"
+    back.save(str(g))
+    assert g.read_text() == f.read_text()
+    with pytest.raises(P.ElpaError):
+        back.best()                                    # nothing timed yet
+    bad = tmp_path / "bad.txt"
+    bad.write_text("elpa_hh_autotune 1\n0 0 100 100 64 0 1\n3 63 0 0 1 -1\n")   # k = 63
+    with pytest.raises(P.ElpaError):
+        P.Autotune.load(str(bad))
+    with pytest.raises(P.ElpaError):
+        P.Autotune(5, 1000, 1000, 64, P.R64)
+    with pytest.raises(P.ElpaError):
+        P.Autotune(P.AUTOTUNE_FAST, 1000, 1000, 64, P.R64, path=P.PATH_WY, k=63)

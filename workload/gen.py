@@ -15,10 +15,13 @@ synthetic_reflectors(...)    random unit-norm-preserving Householder reflectors
 gaussian_block(n, nev, ...)  a dense n x nev block standing in for eigenvectors
 device_reflectors, device_block   the same drawn on the GPU with torch (served
                              stream throughput runs)
+synthetic_stage1(n, b, ...)  first-stage (full -> band) reflectors in the layout
+                             of the band -> full back-transformation
 
 Workload sizes and traces
 -------------------------
-batched_sizes, scf_sequence_sizes, scf_trace (Poisson arrivals, fp32 share)
+batched_sizes, scf_sequence_sizes, scf_trace (Poisson arrivals, fp32 share or a
+switch from fp32 to fp64 at a given SCF step)
 
 The synthetic reflectors have the structure of the real ones: v[0] = 1, the
 other L-1 entries of size about 1/sqrt(b), zero padding past L, and a tau that
@@ -143,20 +146,27 @@ def scf_sequence_sizes(count=64, lo=1000, hi=6000, seed=501):
     return _rng(seed).integers(lo, hi + 1, size=count)
 
 
-def scf_trace(nseq=64, steps=20, rate=200.0, p32=0.25, seed_arrivals=502, seed_dtypes=503):
+def scf_trace(nseq=64, steps=20, rate=200.0, p32=0.25, seed_arrivals=502, seed_dtypes=503,
+              switch_step=None):
     """Arrival trace of the served SCF stream: nseq sequences of `steps` solves.
 
     A Poisson process of the given rate (requests per second) gives
     nseq*steps arrival times; request i belongs to sequence i % nseq as its
     step i // nseq (each sequence's solves arrive in order, and a solve is
     also held back until the sequence's previous solve has completed).  Each
-    request is fp32 with probability p32, else fp64.  Returns
+    request is fp32 with probability p32, else fp64; with switch_step given
+    instead, a sequence's steps before switch_step are fp32 and the rest fp64
+    (single precision while the SCF cycle is far from convergence, double for
+    the final steps, the switching of Kus et al., Sec. 5.2).  Returns
     (arrival seconds, sequence, step, is_fp32) arrays.
     """
     total = nseq * steps
     t = np.cumsum(_rng(seed_arrivals).exponential(1.0 / rate, size=total))
     i = np.arange(total)
-    fp32 = _rng(seed_dtypes).random(total) < p32
+    if switch_step is not None:
+        fp32 = (i // nseq) < switch_step
+    else:
+        fp32 = _rng(seed_dtypes).random(total) < p32
     return t - t[0], i % nseq, i // nseq, fp32
 
 
