@@ -83,6 +83,8 @@ def library():
         L.elpa_hh_autotune_candidates.restype = i64
         L.elpa_hh_autotune_free.argtypes = [p]
         L.elpa_hh_autotune_free.restype = None
+        L.elpa_full_to_band.argtypes = [i64, i64, p, i64, p, i64, p, i32, p]
+        L.elpa_full_to_band.restype = C.c_int
         L.elpa_band_to_tridiag.argtypes = [i64, i64, p, i64, p, p, p, p, i32, p]
         L.elpa_band_to_tridiag.restype = C.c_int
         L.elpa_bt2_trafo.argtypes = [i64, i64, i64, p, i64, p, p, i64, i32, p, i64]
@@ -508,3 +510,37 @@ class Autotune:
             self.close()
         except Exception:
             pass
+
+
+def full_to_band(a, nbw, stream=None):
+    """Full -> band reduction on the device (include/elpa_f2b.h).
+
+    a: (n, n) column-major device tensor (float64 or complex128), a Hermitian
+       matrix in full storage; overwritten with the band matrix (the input of
+       band_to_tridiag).
+    Returns (v, tau): the reflectors in bt2_trafo's layout, device tensors of
+    a's dtype (v column major, n x max(n-nbw, 1)).
+    """
+    import torch
+    if a.dim() != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("a must be square")
+    n = a.shape[0]
+    if n > 1 and a.stride(0) != 1:
+        raise ValueError("a must be column major (stride(0) == 1)")
+    lda = a.stride(1) if n > 1 else 1
+    N = max(n - nbw, 1)
+    v = torch.zeros((N, n), dtype=a.dtype, device=a.device).t()
+    tau = torch.zeros(N, dtype=a.dtype, device=a.device)
+    if stream is None:
+        st = torch.cuda.current_stream(a.device).cuda_stream if a.is_cuda else 0
+    elif isinstance(stream, int):
+        st = stream
+    else:
+        st = stream.cuda_stream
+    rc = int(library().elpa_full_to_band(n, nbw, C.c_void_p(a.data_ptr()), lda,
+                                         C.c_void_p(v.data_ptr()), max(n, 1),
+                                         C.c_void_p(tau.data_ptr()), _dtype_code(a),
+                                         C.c_void_p(st)))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    return v, tau

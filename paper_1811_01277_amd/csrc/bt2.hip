@@ -28,38 +28,9 @@
 
 #include "../../include/elpa_bt2.h"
 #include "../../include/elpa_hh.h"
+#include "wy_blas.h"
 
 namespace ebt {
-
-struct zc {
-  double re, im;
-};
-
-template <typename E>
-struct Num;
-template <>
-struct Num<double> {
-  static __device__ __forceinline__ double zero() { return 0.0; }
-  static __device__ __forceinline__ double one() { return 1.0; }
-  static __device__ __forceinline__ double mul(double a, double b) { return a * b; }
-  static __device__ __forceinline__ double add(double a, double b) { return a + b; }
-};
-template <>
-struct Num<float> {
-  static __device__ __forceinline__ float zero() { return 0.0f; }
-  static __device__ __forceinline__ float one() { return 1.0f; }
-  static __device__ __forceinline__ float mul(float a, float b) { return a * b; }
-  static __device__ __forceinline__ float add(float a, float b) { return a + b; }
-};
-template <>
-struct Num<zc> {
-  static __device__ __forceinline__ zc zero() { return {0.0, 0.0}; }
-  static __device__ __forceinline__ zc one() { return {1.0, 0.0}; }
-  static __device__ __forceinline__ zc mul(zc a, zc b) {
-    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-  }
-  static __device__ __forceinline__ zc add(zc a, zc b) { return {a.re + b.re, a.im + b.im}; }
-};
 
 // Vp (m x wb, column major, ld m): column i = v_{c0+i} from row c0+nbw down,
 // zero above row i, one at row i.
@@ -83,136 +54,7 @@ __global__ __launch_bounds__(256) void k_pack(const E* __restrict__ V, int64_t l
   }
 }
 
-// M = I + diag(tau) striu(G) (wb x wb, column major), G = V^H V (ld wb).
-template <typename E>
-__global__ __launch_bounds__(256) void k_unit_tri(const E* __restrict__ G,
-                                                  const E* __restrict__ tau, int64_t wb,
-                                                  E* __restrict__ M) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= wb * wb) return;
-  const int64_t j = e % wb, i = e / wb;
-  M[e] = j < i ? Num<E>::mul(tau[j], G[e]) : (j == i ? Num<E>::one() : Num<E>::zero());
-}
-
-// out[e] = scale(e) * sum_s part[s][e] over cnt partial products of `total`
-// elements each (fixed order: the same bits on every call); scale is tau[e %
-// wb] when tau is given (the row scaling of W), else 1.
-template <typename E>
-__global__ __launch_bounds__(256) void k_sum_parts(const E* __restrict__ part, int64_t cnt,
-                                                   int64_t total, const E* __restrict__ tau,
-                                                   int64_t wb, E* __restrict__ out) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    E acc = part[e];
-    for (int64_t k = 1; k < cnt; ++k) acc = Num<E>::add(acc, part[k * total + e]);
-    out[e] = tau ? Num<E>::mul(tau[e % wb], acc) : acc;
-  }
-}
-
-// rocBLAS per element type
-template <typename E>
-struct Blas;
-template <>
-struct Blas<double> {
-  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                             int64_t m, int64_t n, int64_t k, double alpha, const double* A,
-                             int64_t lda, const double* B, int64_t ldb, double beta, double* C,
-                             int64_t ldc) {
-    return rocblas_dgemm_64(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc);
-  }
-  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                                int64_t m, int64_t n, int64_t k, double alpha, const double* A,
-                                int64_t lda, int64_t sa, const double* B, int64_t ldb, int64_t sb,
-                                double beta, double* C, int64_t ldc, int64_t sc, int64_t cnt) {
-    return rocblas_dgemm_strided_batched_64(h, ta, tb, m, n, k, &alpha, A, lda, sa, B, ldb, sb,
-                                            &beta, C, ldc, sc, cnt);
-  }
-  static rocblas_status trsm_unit_upper(rocblas_handle h, int64_t m, int64_t n, const double* A,
-                                        int64_t lda, double* B, int64_t ldb) {
-    const double one = 1.0;
-    return rocblas_dtrsm_64(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                            rocblas_diagonal_unit, m, n, &one, A, lda, B, ldb);
-  }
-  static constexpr rocblas_operation adj = rocblas_operation_transpose;
-};
-template <>
-struct Blas<float> {
-  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                             int64_t m, int64_t n, int64_t k, float alpha, const float* A,
-                             int64_t lda, const float* B, int64_t ldb, float beta, float* C,
-                             int64_t ldc) {
-    return rocblas_sgemm_64(h, ta, tb, m, n, k, &alpha, A, lda, B, ldb, &beta, C, ldc);
-  }
-  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                                int64_t m, int64_t n, int64_t k, float alpha, const float* A,
-                                int64_t lda, int64_t sa, const float* B, int64_t ldb, int64_t sb,
-                                float beta, float* C, int64_t ldc, int64_t sc, int64_t cnt) {
-    return rocblas_sgemm_strided_batched_64(h, ta, tb, m, n, k, &alpha, A, lda, sa, B, ldb, sb,
-                                            &beta, C, ldc, sc, cnt);
-  }
-  static rocblas_status trsm_unit_upper(rocblas_handle h, int64_t m, int64_t n, const float* A,
-                                        int64_t lda, float* B, int64_t ldb) {
-    const float one = 1.0f;
-    return rocblas_strsm_64(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                            rocblas_diagonal_unit, m, n, &one, A, lda, B, ldb);
-  }
-  static constexpr rocblas_operation adj = rocblas_operation_transpose;
-};
-template <>
-struct Blas<zc> {
-  static rocblas_status gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                             int64_t m, int64_t n, int64_t k, double alpha, const zc* A,
-                             int64_t lda, const zc* B, int64_t ldb, double beta, zc* C,
-                             int64_t ldc) {
-    const rocblas_double_complex a{alpha, 0.0}, b{beta, 0.0};
-    return rocblas_zgemm_64(h, ta, tb, m, n, k, &a, (const rocblas_double_complex*)A, lda,
-                            (const rocblas_double_complex*)B, ldb, &b,
-                            (rocblas_double_complex*)C, ldc);
-  }
-  static rocblas_status gemm_sb(rocblas_handle h, rocblas_operation ta, rocblas_operation tb,
-                                int64_t m, int64_t n, int64_t k, double alpha, const zc* A,
-                                int64_t lda, int64_t sa, const zc* B, int64_t ldb, int64_t sb,
-                                double beta, zc* C, int64_t ldc, int64_t sc, int64_t cnt) {
-    const rocblas_double_complex a{alpha, 0.0}, b{beta, 0.0};
-    return rocblas_zgemm_strided_batched_64(h, ta, tb, m, n, k, &a,
-                                            (const rocblas_double_complex*)A, lda, sa,
-                                            (const rocblas_double_complex*)B, ldb, sb, &b,
-                                            (rocblas_double_complex*)C, ldc, sc, cnt);
-  }
-  static rocblas_status trsm_unit_upper(rocblas_handle h, int64_t m, int64_t n, const zc* A,
-                                        int64_t lda, zc* B, int64_t ldb) {
-    const rocblas_double_complex one{1.0, 0.0};
-    return rocblas_ztrsm_64(h, rocblas_side_left, rocblas_fill_upper, rocblas_operation_none,
-                            rocblas_diagonal_unit, m, n, &one, (const rocblas_double_complex*)A,
-                            lda, (rocblas_double_complex*)B, ldb);
-  }
-  static constexpr rocblas_operation adj = rocblas_operation_conjugate_transpose;
-};
-
-// One rocBLAS handle per device; calls on a device are serialised (a handle
-// holds one stream at a time).
-struct Handles {
-  std::mutex mu;
-  std::vector<rocblas_handle> h;
-  static Handles& get() {
-    static Handles x;
-    return x;
-  }
-};
-
 int64_t default_block(int32_t dtype) { return dtype == ELPA_C64 ? 192 : 384; }
-
-// K chunks of the products with a long contraction (V^H Q, V^H V: wb x N
-// outputs, m rows): enough chunks that chunks x output tiles fill the device,
-// chunks of at least 256 rows, partial products within 512 MiB.
-int64_t ksplit(int64_t m, int64_t wb, int64_t N, size_t es) {
-  const int64_t tiles = ((wb + 127) / 128) * ((N + 127) / 128);
-  int64_t S = (768 + tiles - 1) / tiles;
-  S = std::min<int64_t>(S, std::max<int64_t>(1, m / 256));
-  const int64_t cap =
-      std::max<int64_t>(1, (int64_t)((size_t(512) << 20) / ((size_t)wb * (size_t)N * es)));
-  return std::max<int64_t>(1, std::min(S, cap));
-}
 
 struct Layout {
   int64_t N = 0, w = 0, mmax = 0, nev = 0;
@@ -248,32 +90,6 @@ size_t elem_size(int32_t dtype) {
   }
 }
 
-// C (wb x N) = A^H B over m rows (A m x wb, lda; B m x N, ldb) as `chunks`
-// K-chunk partial products in part, summed in a fixed order; rows of C
-// scaled by tau when given.
-template <typename E, typename S>
-bool gemm_adj_splitk(rocblas_handle h, int64_t wb, int64_t N, int64_t m, const E* A, int64_t lda,
-                     const E* B, int64_t ldb, int64_t chunks, E* part, const E* tau, E* C,
-                     hipStream_t st) {
-  const int64_t kc = (m + chunks - 1) / chunks;
-  const int64_t full = m / kc, rem = m - full * kc;
-  const auto A_ = Blas<E>::adj;
-  const auto N_ = rocblas_operation_none;
-  bool ok = true;
-  if (full > 0)
-    ok = Blas<E>::gemm_sb(h, A_, N_, wb, N, kc, S(1), A, lda, kc, B, ldb, kc, S(0), part, wb,
-                          wb * N, full) == rocblas_status_success;
-  if (ok && rem > 0)
-    ok = Blas<E>::gemm(h, A_, N_, wb, N, rem, S(1), A + full * kc, lda, B + full * kc, ldb, S(0),
-                       part + full * wb * N, wb) == rocblas_status_success;
-  if (ok) {
-    const int64_t total = wb * N;
-    hipLaunchKernelGGL(k_sum_parts<E>, dim3((unsigned)std::min<int64_t>((total + 255) / 256, 8192)),
-                       dim3(256), 0, st, part, full + (rem > 0 ? 1 : 0), total, tau, wb, C);
-  }
-  return ok;
-}
-
 template <typename E, typename S>
 int run(int64_t n, int64_t nev, int64_t nbw, const E* V, int64_t ldv, const E* tau, E* Q,
         int64_t ldq, hipStream_t st, int64_t block) {
@@ -285,19 +101,11 @@ int run(int64_t n, int64_t nev, int64_t nbw, const E* V, int64_t ldv, const E* t
   E* M = (E*)(ws + L.vp + L.g);
   E* W = (E*)(ws + L.vp + L.g + L.t);
   E* part = (E*)(ws + L.vp + L.g + L.t + L.wbuf);
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  Handles& H = Handles::get();
   int rc = ELPA_OK;
   {
-    std::lock_guard<std::mutex> lock(H.mu);
-    if ((size_t)dev >= H.h.size()) H.h.resize((size_t)dev + 1, nullptr);
-    if (!H.h[(size_t)dev] && rocblas_create_handle(&H.h[(size_t)dev]) != rocblas_status_success) {
-      H.h[(size_t)dev] = nullptr;
-      rc = ELPA_ERR_DEVICE;
-    }
-    rocblas_handle h = H.h[(size_t)dev];
-    if (rc == ELPA_OK && rocblas_set_stream(h, st) != rocblas_status_success) rc = ELPA_ERR_DEVICE;
+    std::lock_guard<std::mutex> lock(Handles::get().mu);
+    rocblas_handle h = handle_for(st);
+    if (!h) rc = ELPA_ERR_DEVICE;
     const int64_t nblk = (L.N + L.w - 1) / L.w;
     for (int64_t b = nblk - 1; rc == ELPA_OK && b >= 0; --b) {
       const int64_t c0 = b * L.w;
@@ -317,7 +125,8 @@ int run(int64_t n, int64_t nev, int64_t nbw, const E* V, int64_t ldv, const E* t
       // W = diag(tau) V^H Q[c0+nbw:, :], then W <- M^{-1} W (= T V^H Q)
       ok = ok && gemm_adj_splitk<E, S>(h, wb, nev, m, Vp, m, Qs, ldq,
                                        ksplit(m, wb, nev, sizeof(E)), part, tau + c0, W, st);
-      ok = ok && Blas<E>::trsm_unit_upper(h, wb, nev, M, wb, W, wb) == rocblas_status_success;
+      ok = ok && Blas<E>::trsm(h, rocblas_side_left, rocblas_operation_none, wb, nev, M, wb, W,
+                               wb) == rocblas_status_success;
       ok = ok && Blas<E>::gemm(h, N_, N_, m, nev, wb, S(-1), Vp, m, W, wb, S(1), Qs, ldq) ==
                      rocblas_status_success;
       if (!ok || hipGetLastError() != hipSuccess) rc = ELPA_ERR_DEVICE;

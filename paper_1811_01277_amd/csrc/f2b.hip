@@ -1,0 +1,328 @@
+// Full -> band reduction (C ABI in include/elpa_f2b.h; Kus et al., Sec. 2).
+//
+// Panel p: the m = n-p-nbw rows below the band of columns [p, p+nbw) get a
+// Householder QR, one column at a time, spread over G workgroups of 256 rows
+// each, two launches per column and no waiting between workgroups:
+//   reflect(i): every workgroup sums the G partial norms of column p+i in a
+//     fixed order and derives the same larfg result (tau, beta, scale); it
+//     scales its rows of the column into V (zeros above the unit lead) and
+//     writes its partial products conj(v)^T A[:, p+j] for the panel's later
+//     columns;
+//   update(i): every workgroup sums those partials in a fixed order, applies
+//     the reflector to its rows of the later columns, writes beta and the
+//     zeros of column p+i, and the partial norms of column p+i+1.
+// The panel is then mirrored into the rows above (Hermitian storage), and the
+// trailing matrix A22 = A[p+nbw:, p+nbw:] is updated from both sides with the
+// panel's compact-WY product Q = I - V T V^H, T = M^{-1} diag(tau),
+// M = I + diag(tau) striu(V^H V):
+//   A22 <- Q^H A22 = A22 - V diag(conj tau) M^{-H} (V^H A22),
+//   A22 <- A22 Q   = A22 - ((A22 V) M^{-1} diag(tau)) V^H,
+// as GEMMs and triangular solves on the matrix cores (rocBLAS).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "../../include/elpa_f2b.h"
+#include "../../include/elpa_hh.h"
+#include "wy_blas.h"
+
+namespace ef2b {
+
+using ebt::Blas;
+using ebt::Num;
+using ebt::zc;
+
+__device__ __forceinline__ double conj_(double a) { return a; }
+__device__ __forceinline__ zc conj_(zc a) { return zc{a.re, -a.im}; }
+__device__ __forceinline__ double sub(double a, double b) { return a - b; }
+__device__ __forceinline__ zc sub(zc a, zc b) { return zc{a.re - b.re, a.im - b.im}; }
+__device__ __forceinline__ double abs2(double a) { return a * a; }
+__device__ __forceinline__ double abs2(zc a) { return a.re * a.re + a.im * a.im; }
+__device__ __forceinline__ double re(double a) { return a; }
+__device__ __forceinline__ double re(zc a) { return a.re; }
+__device__ __forceinline__ double im(double) { return 0.0; }
+__device__ __forceinline__ double im(zc a) { return a.im; }
+template <typename E>
+__device__ __forceinline__ E from_re(double x) {
+  if constexpr (std::is_same<E, double>::value)
+    return x;
+  else
+    return zc{x, 0.0};
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) x += __shfl_xor(x, w, 64);
+  return x;
+}
+__device__ __forceinline__ zc wave_sum(zc x) { return zc{wave_sum(x.re), wave_sum(x.im)}; }
+
+constexpr int kRows = 256;  // panel rows per workgroup (one per thread)
+constexpr int kMaxNb = 256;
+
+// sum over the workgroup's threads (4 waves); every thread gets the total
+template <typename T>
+__device__ __forceinline__ T block_sum(T x, T* red) {
+  x = wave_sum(x);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = x;
+  __syncthreads();
+  T t = red[0];
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) t = Num<T>::add(t, red[w]);
+  return t;
+}
+
+// partial norms sum |A[r0+row, col]|^2 over the group's rows with row > i
+template <typename E>
+__global__ __launch_bounds__(kRows) void k_pnorm(const E* __restrict__ A, int64_t lda, int64_t r0,
+                                                 int64_t col, int64_t m, int64_t i,
+                                                 double* __restrict__ pn) {
+  __shared__ double red[4];
+  const int64_t row = (int64_t)blockIdx.x * kRows + threadIdx.x;
+  const double x = (row < m && row > i) ? abs2(A[r0 + row + col * lda]) : 0.0;
+  const double t = block_sum(x, red);
+  if (threadIdx.x == 0) pn[blockIdx.x] = t;
+}
+
+// larfg of column p+i from the partial norms: every group derives the same
+// (tau, beta, scale)
+template <typename E>
+__device__ __forceinline__ void larfg_from(const E* __restrict__ A, int64_t lda, int64_t r0,
+                                           int64_t p, int64_t i, int G,
+                                           const double* __restrict__ pn, E* tau_out,
+                                           double* beta_out, E* scale_out) {
+  double sum = 0.0;
+  for (int g = 0; g < G; ++g) sum += pn[g];
+  const E alpha = A[r0 + i + (p + i) * lda];
+  const double ar = re(alpha), ai = im(alpha);
+  if (sum == 0.0 && ai == 0.0) {
+    *tau_out = from_re<E>(0.0);
+    *beta_out = ar;
+    *scale_out = from_re<E>(1.0);
+    return;
+  }
+  const double h = sqrt(ar * ar + ai * ai + sum);
+  const double bt = (ar >= 0.0) ? -h : h;
+  if constexpr (std::is_same<E, double>::value) {
+    *tau_out = (bt - ar) / bt;
+    *scale_out = 1.0 / (alpha - bt);
+  } else {
+    *tau_out = zc{(bt - ar) / bt, -ai / bt};
+    const zc den{alpha.re - bt, alpha.im};
+    const double dd = den.re * den.re + den.im * den.im;
+    *scale_out = zc{den.re / dd, -den.im / dd};
+  }
+  *beta_out = bt;
+}
+
+template <typename E>
+__global__ __launch_bounds__(kRows) void k_reflect(const E* __restrict__ A, int64_t lda,
+                                                   int64_t r0, int64_t p, int64_t m, int64_t b,
+                                                   int64_t i, int G, const double* __restrict__ pn,
+                                                   E* __restrict__ V, int64_t ldv,
+                                                   E* __restrict__ tau, E* __restrict__ pd) {
+  __shared__ E sh[2];
+  __shared__ E red[4];
+  if (threadIdx.x == 0) {
+    E t, s;
+    double beta;
+    larfg_from(A, lda, r0, p, i, G, pn, &t, &beta, &s);
+    sh[0] = t;
+    sh[1] = s;
+    if (blockIdx.x == 0) tau[p + i] = t;
+  }
+  __syncthreads();
+  const E sc = sh[1];
+  const int64_t row = (int64_t)blockIdx.x * kRows + threadIdx.x;
+  E v = from_re<E>(0.0);
+  if (row < m) {
+    if (row > i)
+      v = Num<E>::mul(A[r0 + row + (p + i) * lda], sc);
+    else if (row == i)
+      v = from_re<E>(1.0);
+    V[r0 + row + (p + i) * ldv] = v;  // zeros above the unit lead
+  }
+  const E cv = conj_(v);
+  for (int64_t j = i + 1; j < b; ++j) {
+    const E x = (row < m && row >= i) ? Num<E>::mul(cv, A[r0 + row + (p + j) * lda])
+                                      : from_re<E>(0.0);
+    const E t = block_sum(x, red);
+    if (threadIdx.x == 0) pd[(int64_t)blockIdx.x * b + j] = t;
+  }
+}
+
+template <typename E>
+__global__ __launch_bounds__(kRows) void k_update(E* __restrict__ A, int64_t lda, int64_t r0,
+                                                  int64_t p, int64_t m, int64_t b, int64_t i,
+                                                  int G, const E* __restrict__ V, int64_t ldv,
+                                                  const E* __restrict__ tau,
+                                                  const double* __restrict__ pn_in,
+                                                  const E* __restrict__ pd,
+                                                  double* __restrict__ pn_out, int64_t k) {
+  __shared__ E coef[kMaxNb];
+  __shared__ double shb;
+  __shared__ double red[4];
+  const E ct = conj_(tau[p + i]);
+  for (int64_t j = i + 1 + threadIdx.x; j < b; j += blockDim.x) {
+    E w = pd[j];
+    for (int g = 1; g < G; ++g) w = Num<E>::add(w, pd[(int64_t)g * b + j]);
+    coef[j] = Num<E>::mul(ct, w);
+  }
+  if (threadIdx.x == 0) {
+    E t, s;
+    double beta;
+    larfg_from(A, lda, r0, p, i, G, pn_in, &t, &beta, &s);
+    shb = beta;
+  }
+  __syncthreads();
+  const int64_t row = (int64_t)blockIdx.x * kRows + threadIdx.x;
+  if (row < m && row >= i) {
+    const E v = (row == i) ? from_re<E>(1.0) : V[r0 + row + (p + i) * ldv];
+    for (int64_t j = i + 1; j < b; ++j) {
+      E& a = A[r0 + row + (p + j) * lda];
+      a = sub(a, Num<E>::mul(v, coef[j]));
+    }
+    A[r0 + row + (p + i) * lda] = (row == i) ? from_re<E>(shb) : from_re<E>(0.0);
+  }
+  if (i + 1 < k) {  // partial norms of the next column, rows > i+1
+    const double x = (row < m && row > i + 1) ? abs2(A[r0 + row + (p + i + 1) * lda]) : 0.0;
+    const double t = block_sum(x, red);
+    if (threadIdx.x == 0) pn_out[blockIdx.x] = t;
+  }
+}
+
+// A[p+j, r0+row] = conj(A[r0+row, p+j]) for the panel
+template <typename E>
+__global__ __launch_bounds__(256) void k_mirror(E* __restrict__ A, int64_t lda, int64_t r0,
+                                                int64_t p, int64_t m, int64_t b) {
+  const int64_t j = blockIdx.y;
+  for (int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; row < m;
+       row += (int64_t)gridDim.x * blockDim.x)
+    A[p + j + (r0 + row) * lda] = conj_(A[r0 + row + (p + j) * lda]);
+}
+
+// W (rows x cols, ld) scaled: by_rows: W[r, c] *= conj(tau[r]); else W[r, c] *= tau[c]
+template <typename E>
+__global__ __launch_bounds__(256) void k_scale(E* __restrict__ W, int64_t ld, int64_t rows,
+                                               int64_t cols, const E* __restrict__ tau,
+                                               bool by_rows) {
+  const int64_t total = rows * cols;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e % rows, c = e / rows;
+    E& w = W[r + c * ld];
+    w = Num<E>::mul(by_rows ? conj_(tau[r]) : tau[c], w);
+  }
+}
+
+template <typename E>
+int run(int64_t n, int64_t b, E* A, int64_t lda, E* V, int64_t ldv, E* tau, hipStream_t st) {
+  using S = typename std::conditional<std::is_same<E, float>::value, float, double>::type;
+  const size_t es = sizeof(E);
+  const int64_t mmax = n - b;
+  const int Gmax = (int)((mmax + kRows - 1) / kRows);
+  auto al = [](size_t x) { return (x + 255) / 256 * 256; };
+  size_t part_e = 0;  // the largest set of K-chunk partial products over the panels
+  for (int64_t p = 0; p + b < n; p += b) {
+    const int64_t m = n - p - b, k = std::min(b, m);
+    part_e = std::max(part_e, (size_t)ebt::ksplit(m, k, k, es) * k * k);
+    part_e = std::max(part_e, (size_t)ebt::ksplit(m, k, m, es) * k * m);
+  }
+  const size_t off_pn = 0, off_pd = off_pn + al(2 * Gmax * sizeof(double) + 512),
+               off_g = off_pd + al((size_t)Gmax * b * es), off_m = off_g + al((size_t)b * b * es),
+               off_w1 = off_m + al((size_t)b * b * es), off_w2 = off_w1 + al((size_t)b * mmax * es),
+               off_part = off_w2 + al((size_t)mmax * b * es), total = off_part + al(part_e * es);
+  char* ws = nullptr;
+  if (hipMallocAsync((void**)&ws, total, st) != hipSuccess) return ELPA_ERR_NOMEM;
+  double* pn0 = (double*)(ws + off_pn);
+  double* pn1 = pn0 + Gmax;
+  E* pd = (E*)(ws + off_pd);
+  E* Gm = (E*)(ws + off_g);
+  E* M = (E*)(ws + off_m);
+  E* W1 = (E*)(ws + off_w1);
+  E* W2 = (E*)(ws + off_w2);
+  E* part = (E*)(ws + off_part);
+  int rc = ELPA_OK;
+  {
+    std::lock_guard<std::mutex> lock(ebt::Handles::get().mu);
+    rocblas_handle h = ebt::handle_for(st);
+    if (!h) rc = ELPA_ERR_DEVICE;
+    const auto N_ = rocblas_operation_none;
+    const auto C_ = Blas<E>::adj;
+    for (int64_t p = 0; rc == ELPA_OK && p + b < n; p += b) {
+      const int64_t r0 = p + b, m = n - r0, k = std::min(b, m);
+      const int G = (int)((m + kRows - 1) / kRows);
+      double* pa = pn0;
+      double* pb = pn1;
+      hipLaunchKernelGGL(k_pnorm<E>, dim3(G), dim3(kRows), 0, st, (const E*)A, lda, r0, p, m,
+                         (int64_t)0, pa);
+      for (int64_t i = 0; i < k; ++i) {
+        hipLaunchKernelGGL(k_reflect<E>, dim3(G), dim3(kRows), 0, st, (const E*)A, lda, r0, p, m,
+                           b, i, G, (const double*)pa, V, ldv, tau, pd);
+        hipLaunchKernelGGL(k_update<E>, dim3(G), dim3(kRows), 0, st, A, lda, r0, p, m, b, i, G,
+                           (const E*)V, ldv, (const E*)tau, (const double*)pa, (const E*)pd, pb,
+                           k);
+        std::swap(pa, pb);
+      }
+      hipLaunchKernelGGL(k_mirror<E>, dim3((unsigned)std::min<int64_t>((m + 255) / 256, 1024),
+                                           (unsigned)b),
+                         dim3(256), 0, st, A, lda, r0, p, m, b);
+      // trailing update with the panel's k reflectors
+      const E* Vp = V + r0 + p * ldv;
+      E* A22 = A + r0 + r0 * lda;
+      const E* tp = tau + p;
+      bool ok = ebt::gemm_adj_splitk<E, S>(h, k, k, m, Vp, ldv, Vp, ldv,
+                                           ebt::ksplit(m, k, k, es), part, nullptr, Gm, st);
+      if (ok)
+        hipLaunchKernelGGL(ebt::k_unit_tri<E>, dim3((unsigned)((k * k + 255) / 256)), dim3(256),
+                           0, st, (const E*)Gm, tp, k, M);
+      // left: W1 = diag(conj tau) M^{-H} (V^H A22), A22 -= V W1
+      ok = ok && ebt::gemm_adj_splitk<E, S>(h, k, m, m, Vp, ldv, A22, lda,
+                                            ebt::ksplit(m, k, m, es), part, nullptr, W1, st);
+      ok = ok && Blas<E>::trsm(h, rocblas_side_left, C_, k, m, M, k, W1, k) ==
+                     rocblas_status_success;
+      if (ok)
+        hipLaunchKernelGGL(k_scale<E>, dim3((unsigned)std::min<int64_t>((k * m + 255) / 256, 4096)),
+                           dim3(256), 0, st, W1, k, k, m, tp, true);
+      ok = ok && Blas<E>::gemm(h, N_, N_, m, m, k, S(-1), Vp, ldv, W1, k, S(1), A22, lda) ==
+                     rocblas_status_success;
+      // right: W2 = (A22 V) M^{-1} diag(tau), A22 -= W2 V^H
+      ok = ok && Blas<E>::gemm(h, N_, N_, m, k, m, S(1), A22, lda, Vp, ldv, S(0), W2, m) ==
+                     rocblas_status_success;
+      ok = ok && Blas<E>::trsm(h, rocblas_side_right, N_, m, k, M, k, W2, m) ==
+                     rocblas_status_success;
+      if (ok)
+        hipLaunchKernelGGL(k_scale<E>, dim3((unsigned)std::min<int64_t>((k * m + 255) / 256, 4096)),
+                           dim3(256), 0, st, W2, m, m, k, tp, false);
+      ok = ok && Blas<E>::gemm(h, N_, C_, m, m, k, S(-1), W2, m, Vp, ldv, S(1), A22, lda) ==
+                     rocblas_status_success;
+      if (!ok || hipGetLastError() != hipSuccess) rc = ELPA_ERR_DEVICE;
+    }
+  }
+  const hipError_t e2 = hipFreeAsync(ws, st);
+  if (rc == ELPA_OK && e2 != hipSuccess) rc = ELPA_ERR_DEVICE;
+  return rc;
+}
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+}  // namespace ef2b
+
+extern "C" int elpa_full_to_band(int64_t n, int64_t nbw, void* A, int64_t lda, void* V,
+                                 int64_t ldv, void* tau, int32_t dtype, void* stream) {
+  if (dtype != ELPA_R64 && dtype != ELPA_C64) return ELPA_ERR_DTYPE;
+  if (n < 1 || nbw < 1 || nbw > ef2b::kMaxNb || lda < n || ldv < n) return ELPA_ERR_ARG;
+  if (!A) return ELPA_ERR_ARG;
+  if (n <= nbw) return ELPA_OK;
+  if (!V || !tau) return ELPA_ERR_ARG;
+  const size_t es = dtype == ELPA_C64 ? 16 : 8;
+  if (!ef2b::aligned(A, es) || !ef2b::aligned(V, es) || !ef2b::aligned(tau, es))
+    return ELPA_ERR_ALIGN;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  if (dtype == ELPA_R64)
+    return ef2b::run<double>(n, nbw, (double*)A, lda, (double*)V, ldv, (double*)tau, st);
+  return ef2b::run<ebt::zc>(n, nbw, (ebt::zc*)A, lda, (ebt::zc*)V, ldv, (ebt::zc*)tau, st);
+}

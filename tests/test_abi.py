@@ -213,3 +213,15 @@ def test_band_to_tridiag_argument_errors():
     assert lib.elpa_band_to_tridiag(10, 513, nul, 10, nul, nul, nul, nul, P.R64, nul) == -1
     assert lib.elpa_band_to_tridiag(10, 2, nul, 9, nul, nul, nul, nul, P.R64, nul) == -1
     assert lib.elpa_band_to_tridiag(10, 2, nul, 10, nul, nul, nul, nul, P.R64, nul) == -1
+
+
+def test_full_to_band_argument_errors():
+    lib = P.library()
+    nul = None
+    assert lib.elpa_full_to_band(10, 2, nul, 10, nul, 10, nul, P.R32, nul) == -2
+    assert lib.elpa_full_to_band(0, 2, nul, 10, nul, 10, nul, P.R64, nul) == -1
+    assert lib.elpa_full_to_band(10, 0, nul, 10, nul, 10, nul, P.R64, nul) == -1
+    assert lib.elpa_full_to_band(10, 257, nul, 10, nul, 10, nul, P.R64, nul) == -1
+    assert lib.elpa_full_to_band(10, 2, nul, 9, nul, 10, nul, P.R64, nul) == -1
+    assert lib.elpa_full_to_band(10, 2, nul, 10, nul, 9, nul, P.R64, nul) == -1
+    assert lib.elpa_full_to_band(10, 2, nul, 10, nul, 10, nul, P.R64, nul) == -1
