@@ -53,6 +53,8 @@ def parse():
                     help="skip the band->full back-transformation leg")
     ap.add_argument("--no-b2t", action="store_true",
                     help="skip the band->tridiagonal reduction leg")
+    ap.add_argument("--no-f2b", action="store_true",
+                    help="skip the full->band reduction leg")
     ap.add_argument("--bt2-only", action="store_true",
                     help="instead of the benchmark: only the band->full leg at --nev "
                          "(for profiling it on its own)")
@@ -250,6 +252,37 @@ def b2t_leg(args):
                         f"matrix", "s": round(t, 3), "chase_steps": steps,
             "steps_per_s": round(steps / t), "launches": launches,
             "us_per_launch": round(t / launches * 1e6, 2)}
+
+
+def f2b_leg(args):
+    """Full -> band reduction (elpa_full_to_band) of a random symmetric matrix
+    of the same n, nbw 64, real fp64, drawn on the device.  Counted flops
+    8 n^3 / 3 (the two-sided trailing update as executed: V^H A22, A22 V and
+    two rank-k updates per panel)."""
+    import torch
+    import paper_1811_01277_amd as P
+    dev = torch.device("cuda:0")
+    n, b = args.n, 64
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + 11)
+    G = torch.randn(n, n, device=dev, dtype=torch.float64, generator=g)
+    A = (G + G.t()) * 0.5
+    del G
+    times = []
+    for _ in range(2):
+        a = A.clone().t()   # symmetric: the column-major view holds the same matrix
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        v, tau = P.full_to_band(a, b)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        del a, v, tau
+    del A
+    torch.cuda.empty_cache()
+    t = min(times)
+    return {"workload": f"full->band reduction, n={n}, nbw={b}, r64, random symmetric "
+                        f"matrix", "s": round(t, 3),
+            "tflops_8n3_3": round(8.0 * n ** 3 / 3 / t / 1e12, 2)}
 
 
 def recorded_traffic(workload):
@@ -453,6 +486,8 @@ def main():
         torch.cuda.empty_cache()
     if not args.no_b2t:
         out["b2t"] = b2t_leg(args)
+    if not args.no_f2b:
+        out["f2b"] = f2b_leg(args)
         torch.cuda.empty_cache()
     if not args.no_served:
         out["served_stream"] = served_stream(args)

@@ -32,7 +32,7 @@ extern "C" {
  * V: device, n x max(n-nbw, 1) elements, column major, ldv >= n (written in
  *    rows [p+nbw, n) of each panel's columns; other entries untouched).
  * tau: device, max(n-nbw, 1) elements.
- * dtype: ELPA_R64 or ELPA_C64; nbw >= 1.  Asynchronous on `stream`; the
+ * dtype: ELPA_R64 or ELPA_C64; 1 <= nbw <= 256, n >= 1.  Asynchronous on `stream`; the
  * library allocates a workspace in stream order.  Returns ELPA_OK or
  * ELPA_ERR_ARG / _DTYPE / _ALIGN / _NOMEM / _DEVICE (elpa_hh.h); arguments
  * are checked before anything is enqueued; n <= nbw leaves A as it is.
