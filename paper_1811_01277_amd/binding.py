@@ -83,6 +83,12 @@ def library():
         L.elpa_hh_autotune_candidates.restype = i64
         L.elpa_hh_autotune_free.argtypes = [p]
         L.elpa_hh_autotune_free.restype = None
+        L.elpa_cholesky_inverse.argtypes = [i64, p, i64, i32, p, p]
+        L.elpa_cholesky_inverse.restype = C.c_int
+        L.elpa_generalized_to_standard.argtypes = [i64, p, i64, p, i64, i32, p]
+        L.elpa_generalized_to_standard.restype = C.c_int
+        L.elpa_generalized_back.argtypes = [i64, i64, p, i64, p, i64, i32, p]
+        L.elpa_generalized_back.restype = C.c_int
         L.elpa_full_to_band.argtypes = [i64, i64, p, i64, p, i64, p, i32, p]
         L.elpa_full_to_band.restype = C.c_int
         L.elpa_band_to_tridiag.argtypes = [i64, i64, p, i64, p, p, p, p, i32, p]
@@ -544,3 +550,75 @@ def full_to_band(a, nbw, stream=None):
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
     return v, tau
+
+
+def _stream_of(t, stream):
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream(t.device).cuda_stream if t.is_cuda else 0
+    return stream if isinstance(stream, int) else stream.cuda_stream
+
+
+def _col_major_ld(x, name):
+    if x.dim() != 2:
+        raise ValueError(f"{name} must be a matrix")
+    if x.shape[0] > 1 and x.stride(0) != 1:
+        raise ValueError(f"{name} must be column major (stride(0) == 1)")
+    return max(x.stride(1) if x.shape[1] > 1 else x.shape[0], 1)
+
+
+def cholesky_inverse(b, stream=None, check=True):
+    """b <- L^{-1} with b = L L^H (include/elpa_gen.h): the inverted Cholesky
+    factor that the generalized solve keeps in b's storage.  b: (n, n)
+    column-major device tensor (float64 or complex128), lower triangle read.
+    With check=True the stream is synchronised and a matrix that is not
+    positive definite raises numpy.linalg.LinAlgError; with check=False the
+    device int32 info tensor is returned (0, or the 1-based order of the
+    first leading minor that is not positive definite)."""
+    import torch
+    if b.dim() != 2 or b.shape[0] != b.shape[1]:
+        raise ValueError("b must be square")
+    n = b.shape[0]
+    ldb = _col_major_ld(b, "b")
+    info = torch.zeros(1, dtype=torch.int32, device=b.device)
+    rc = int(library().elpa_cholesky_inverse(n, C.c_void_p(b.data_ptr()), ldb, _dtype_code(b),
+                                             C.c_void_p(_stream_of(b, stream)),
+                                             C.c_void_p(info.data_ptr())))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    if not check:
+        return info
+    i = int(info.item())
+    if i:
+        import numpy as np
+        raise np.linalg.LinAlgError(f"leading minor of order {i} is not positive definite")
+    return info
+
+
+def generalized_to_standard(a, linv, stream=None):
+    """a <- linv a linv^H, exactly Hermitian (include/elpa_gen.h)."""
+    if a.dim() != 2 or a.shape[0] != a.shape[1] or tuple(linv.shape) != tuple(a.shape):
+        raise ValueError("a and linv must be square of the same size")
+    if linv.dtype != a.dtype:
+        raise ValueError("a and linv must have the same dtype")
+    rc = int(library().elpa_generalized_to_standard(
+        a.shape[0], C.c_void_p(a.data_ptr()), _col_major_ld(a, "a"), C.c_void_p(linv.data_ptr()),
+        _col_major_ld(linv, "linv"), _dtype_code(a), C.c_void_p(_stream_of(a, stream))))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+
+
+def generalized_back(q, linv, stream=None):
+    """q <- linv^H q: the generalized problem's eigenvectors from the standard
+    problem's (include/elpa_gen.h)."""
+    if q.dim() != 2 or linv.dim() != 2 or linv.shape[0] != linv.shape[1] \
+            or linv.shape[0] != q.shape[0]:
+        raise ValueError("q must have as many rows as the square linv")
+    if linv.dtype != q.dtype:
+        raise ValueError("q and linv must have the same dtype")
+    rc = int(library().elpa_generalized_back(
+        q.shape[0], q.shape[1], C.c_void_p(linv.data_ptr()), _col_major_ld(linv, "linv"),
+        C.c_void_p(q.data_ptr()), _col_major_ld(q, "q"), _dtype_code(q),
+        C.c_void_p(_stream_of(q, stream))))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))

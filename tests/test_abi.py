@@ -225,3 +225,26 @@ def test_full_to_band_argument_errors():
     assert lib.elpa_full_to_band(10, 2, nul, 9, nul, 10, nul, P.R64, nul) == -1
     assert lib.elpa_full_to_band(10, 2, nul, 10, nul, 9, nul, P.R64, nul) == -1
     assert lib.elpa_full_to_band(10, 2, nul, 10, nul, 10, nul, P.R64, nul) == -1
+
+
+def test_generalized_argument_errors():
+    """Cholesky inverse and the two generalized transformations: argument
+    checks before anything touches a device; n = 0 is a no-op."""
+    lib = P.library()
+    nul = None
+    assert lib.elpa_cholesky_inverse(10, nul, 10, P.R32, nul, nul) == -2
+    assert lib.elpa_cholesky_inverse(-1, nul, 10, P.R64, nul, nul) == -1
+    assert lib.elpa_cholesky_inverse(10, nul, 9, P.R64, nul, nul) == -1
+    assert lib.elpa_cholesky_inverse(1 << 31, nul, 1 << 31, P.R64, nul, nul) == -1
+    assert lib.elpa_cholesky_inverse(10, nul, 10, P.R64, nul, nul) == -1
+    assert lib.elpa_cholesky_inverse(0, nul, 1, P.C64, nul, nul) == 0
+    assert lib.elpa_generalized_to_standard(10, nul, 10, nul, 10, P.R32, nul) == -2
+    assert lib.elpa_generalized_to_standard(10, nul, 9, nul, 10, P.R64, nul) == -1
+    assert lib.elpa_generalized_to_standard(10, nul, 10, nul, 9, P.R64, nul) == -1
+    assert lib.elpa_generalized_to_standard(10, nul, 10, nul, 10, P.C64, nul) == -1
+    assert lib.elpa_generalized_to_standard(0, nul, 1, nul, 1, P.R64, nul) == 0
+    assert lib.elpa_generalized_back(10, 3, nul, 10, nul, 10, 7, nul) == -2
+    assert lib.elpa_generalized_back(10, -1, nul, 10, nul, 10, P.R64, nul) == -1
+    assert lib.elpa_generalized_back(10, 3, nul, 10, nul, 9, P.R64, nul) == -1
+    assert lib.elpa_generalized_back(10, 3, nul, 10, nul, 10, P.R64, nul) == -1
+    assert lib.elpa_generalized_back(10, 0, nul, 10, nul, 10, P.R64, nul) == 0
