@@ -83,6 +83,8 @@ def library():
         L.elpa_hh_autotune_candidates.restype = i64
         L.elpa_hh_autotune_free.argtypes = [p]
         L.elpa_hh_autotune_free.restype = None
+        L.elpa_tridiag_eigh.argtypes = [i64, i64, p, p, p, p, i64, i32, p]
+        L.elpa_tridiag_eigh.restype = C.c_int
         L.elpa_cholesky_inverse.argtypes = [i64, p, i64, i32, p, p]
         L.elpa_cholesky_inverse.restype = C.c_int
         L.elpa_generalized_to_standard.argtypes = [i64, p, i64, p, i64, i32, p]
@@ -622,3 +624,32 @@ def generalized_back(q, linv, stream=None):
         C.c_void_p(_stream_of(q, stream))))
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
+
+
+def tridiag_eigh(d, e, nev=None, dtype=None, stream=None):
+    """Eigenvalues and eigenvectors of the symmetric tridiagonal matrix
+    (d, e) by divide and conquer on the device (include/elpa_tridiag.h).
+
+    d: (n,) float64 device tensor, e: (n-1,) float64 device tensor.
+    Returns (lam, z): all n eigenvalues ascending, and the eigenvectors of the
+    nev (default n) smallest as an (n, nev) column-major tensor of dtype
+    (float64 default; float32 or complex128 to feed hh_trafo directly)."""
+    import torch
+    n = d.shape[0]
+    nev = n if nev is None else int(nev)
+    dtype = torch.float64 if dtype is None else dtype
+    if d.dtype != torch.float64 or e.dtype != torch.float64:
+        raise TypeError("d and e must be float64")
+    if e.shape[0] != max(n - 1, 0):
+        raise ValueError("e must have n - 1 entries")
+    d = d.contiguous()
+    e = e.contiguous()
+    lam = torch.empty(n, dtype=torch.float64, device=d.device)
+    z = torch.empty((max(nev, 1), max(n, 1)), dtype=dtype, device=d.device).t()[:n, :nev]
+    rc = int(library().elpa_tridiag_eigh(
+        n, nev, C.c_void_p(d.data_ptr()), C.c_void_p(e.data_ptr() if n > 1 else 0),
+        C.c_void_p(lam.data_ptr()), C.c_void_p(z.data_ptr() if nev > 0 else 0), max(n, 1),
+        _dtype_code(z), C.c_void_p(_stream_of(d, stream))))
+    if rc != 0:
+        raise ElpaError(rc, strerror(rc))
+    return lam, z

@@ -13,7 +13,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libelpahip.so")
 SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_split.hip", "hh_wy.hip", "bt2.hip",
-           "b2t.hip", "f2b.hip", "gen.hip"]
+           "b2t.hip", "f2b.hip", "gen.hip", "dc.hip"]
 ARCH = os.environ.get("ELPA_HIP_ARCH", "gfx950")
 
 FLAGS = [

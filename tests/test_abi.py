@@ -248,3 +248,15 @@ def test_generalized_argument_errors():
     assert lib.elpa_generalized_back(10, 3, nul, 10, nul, 9, P.R64, nul) == -1
     assert lib.elpa_generalized_back(10, 3, nul, 10, nul, 10, P.R64, nul) == -1
     assert lib.elpa_generalized_back(10, 0, nul, 10, nul, 10, P.R64, nul) == 0
+
+
+def test_tridiag_eigh_argument_errors():
+    lib = P.library()
+    nul = None
+    assert lib.elpa_tridiag_eigh(10, 3, nul, nul, nul, nul, 10, 5, nul) == -2
+    assert lib.elpa_tridiag_eigh(-1, 0, nul, nul, nul, nul, 10, P.R64, nul) == -1
+    assert lib.elpa_tridiag_eigh(10, 11, nul, nul, nul, nul, 10, P.R64, nul) == -1
+    assert lib.elpa_tridiag_eigh(10, 3, nul, nul, nul, nul, 9, P.R64, nul) == -1
+    assert lib.elpa_tridiag_eigh(10, 3, nul, nul, nul, nul, 10, P.R64, nul) == -1
+    assert lib.elpa_tridiag_eigh(1 << 31, 0, nul, nul, nul, nul, 1 << 31, P.R64, nul) == -1
+    assert lib.elpa_tridiag_eigh(0, 0, nul, nul, nul, nul, 1, P.R64, nul) == 0
