@@ -55,6 +55,11 @@ def parse():
                     help="skip the band->tridiagonal reduction leg")
     ap.add_argument("--no-f2b", action="store_true",
                     help="skip the full->band reduction leg")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the whole-solve leg (every stage of the eigensolver on the device)")
+    ap.add_argument("--solve-only", action="store_true",
+                    help="instead of the benchmark: only the whole-solve leg (for profiling it on "
+                         "its own)")
     ap.add_argument("--bt2-only", action="store_true",
                     help="instead of the benchmark: only the band->full leg at --nev "
                          "(for profiling it on its own)")
@@ -285,6 +290,56 @@ def f2b_leg(args):
             "tflops_8n3_3": round(8.0 * n ** 3 / 3 / t / 1e12, 2)}
 
 
+def solve_leg(args):
+    """The whole standard eigensolver on the device for a random symmetric
+    matrix of the same n, nbw 64, real fp64, the eigenvectors of the nev
+    smallest eigenvalues: full -> band, band -> tridiagonal, tridiagonal
+    divide and conquer, tridiagonal -> band, band -> full.  Stage times with
+    a synchronisation after each, and the residual ratio
+    ||A z - lambda z||_1 / (||A||_1 n eps) on sampled columns."""
+    import torch
+    import paper_1811_01277_amd as P
+    dev = torch.device("cuda:0")
+    n, b, nev = args.n, 64, args.nev
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + 13)
+    A = torch.randn(n, n, device=dev, dtype=torch.float64, generator=g)
+    A = (A + A.t()) * 0.5
+    a = A.clone().t()
+    marks = []
+
+    def mark():
+        torch.cuda.synchronize()
+        marks.append(time.perf_counter())
+
+    mark()
+    v, t1 = P.full_to_band(a, b)
+    mark()
+    d, e, hh, tau = P.band_to_tridiag(a, b)
+    mark()
+    lam, q = P.tridiag_eigh(d, e, nev)
+    mark()
+    P.hh_trafo(q, hh, tau, b)
+    mark()
+    P.bt2_trafo(q, v, t1, b)
+    mark()
+    idx = torch.tensor([0, nev // 2, nev - 1], device=dev)
+    Z = q[:, idx]
+    R = A @ Z - Z * lam[idx]
+    eps = 2.0 ** -52
+    res = float(R.abs().sum(0).max()) / (float(A.abs().sum(0).max()) * n * eps)
+    del A, a, v, t1, d, e, hh, tau, lam, q, Z, R
+    torch.cuda.empty_cache()
+    st = [marks[i + 1] - marks[i] for i in range(5)]
+    return {"workload": f"standard eigensolver on the device, n={n}, nbw={b}, nev={nev}, r64, "
+                        f"random symmetric matrix",
+            "s": round(marks[-1] - marks[0], 3),
+            "stages_s": {"full_to_band": round(st[0], 3), "band_to_tridiag": round(st[1], 3),
+                         "tridiag_eigh": round(st[2], 3), "hh_trafo": round(st[3], 3),
+                         "bt2_trafo": round(st[4], 3)},
+            "residual_ratio_sampled": round(res, 4)}
+
+
 def recorded_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (profiles/*_traffic.json), if they were taken
@@ -387,6 +442,9 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
+    if args.solve_only:
+        print(json.dumps({"solve": solve_leg(args)}), flush=True)
+        return
     if args.bt2_only:
         print(json.dumps({"bt2": bt2_leg(args, [args.nev])}), flush=True)
         return
@@ -488,6 +546,8 @@ def main():
         out["b2t"] = b2t_leg(args)
     if not args.no_f2b:
         out["f2b"] = f2b_leg(args)
+    if not args.no_solve:
+        out["solve"] = solve_leg(args)
         torch.cuda.empty_cache()
     if not args.no_served:
         out["served_stream"] = served_stream(args)

@@ -20,7 +20,8 @@
 //             column's child; rotate: the recorded rotations applied to W;
 //   secular:  root i in (delta_i, delta_i+1) (the last one in (delta_K-1,
 //             delta_K-1 + rho' |w|^2]) as delta_o + tau, o the nearer pole,
-//             by Newton's method kept inside a shrinking bracket;
+//             by Newton's method kept inside a shrinking bracket (one wave
+//             per root, the sums over the poles split over its lanes);
 //   zhat:     w^_j^2 = (lambda_K-1 - delta_j)/rho' prod_{i<j} (lambda_i -
 //             delta_j)/(delta_i - delta_j) prod_{j<=i<K-1} (lambda_i -
 //             delta_j)/(delta_i+1 - delta_j), sign of w_j;
@@ -230,13 +231,21 @@ __global__ __launch_bounds__(256) void k_rotate(const Node* __restrict__ nodes, 
   }
 }
 
-// Root i of 1 + rho sum_j w_j^2 / (delta_j - lambda) = 0, one thread per root.
+__device__ __forceinline__ double wave_sum(double v) {
+  // butterfly: every lane ends with the same bits (a + b == b + a)
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Root i of 1 + rho sum_j w_j^2 / (delta_j - lambda) = 0, one wave per root:
+// the lanes split the sums over j and every lane takes the same decisions.
 __global__ __launch_bounds__(256) void k_secular(const Node* __restrict__ nodes, int64_t per,
                                                  Ws w) {
-  int64_t m, base;
-  split_idx(per, m, base);
+  const int64_t m = (int64_t)blockIdx.x / per;
+  const int lane = threadIdx.x & 63;
+  const int64_t i = ((int64_t)blockIdx.x % per) * 4 + (threadIdx.x >> 6);
   const Node nd = nodes[m];
-  const int64_t lo = nd.lo, i = base + threadIdx.x;
+  const int64_t lo = nd.lo;
   const int64_t K = w.K[m];
   if (i >= K) return;
   const double rho = w.rho[m];
@@ -246,26 +255,30 @@ __global__ __launch_bounds__(256) void k_secular(const Node* __restrict__ nodes,
   double tlo, thi;
   if (i < K - 1) {
     const double a = dl[i], h = 0.5 * (dl[i + 1] - a);
-    double g = 1.0;
-    for (int64_t j = 0; j < K; ++j) g += rho * wv[j] * wv[j] / ((dl[j] - a) - h);
+    double g = 0.0;
+    for (int64_t j = lane; j < K; j += 64) g += wv[j] * wv[j] / ((dl[j] - a) - h);
+    g = 1.0 + rho * wave_sum(g);
     if (g >= 0.0) o = i, tlo = 0.0, thi = h;
     else o = i + 1, tlo = -h, thi = 0.0;
   } else {
     double sw = 0.0;
-    for (int64_t j = 0; j < K; ++j) sw += wv[j] * wv[j];
-    o = i, tlo = 0.0, thi = rho * sw;
+    for (int64_t j = lane; j < K; j += 64) sw += wv[j] * wv[j];
+    o = i, tlo = 0.0, thi = rho * wave_sum(sw);
   }
   const double sg = dl[o];
   double t = 0.5 * (tlo + thi);
   for (int it = 0; it < 200; ++it) {
-    double g = 1.0, gp = 0.0, ab = 0.0;
-    for (int64_t j = 0; j < K; ++j) {
+    double g = 0.0, gp = 0.0, ab = 0.0;
+    for (int64_t j = lane; j < K; j += 64) {
       const double D = (dl[j] - sg) - t;
       const double term = wv[j] * wv[j] / D;
-      g += rho * term;
-      gp += rho * term / D;
+      g += term;
+      gp += term / D;
       ab += fabs(term);
     }
+    g = 1.0 + rho * wave_sum(g);
+    gp = rho * wave_sum(gp);
+    ab = wave_sum(ab);
     if (fabs(g) <= kEps * (double)(K + 1) * (1.0 + rho * ab)) break;
     if (g < 0.0) tlo = t; else thi = t;
     double tn = t - g / gp;
@@ -273,8 +286,10 @@ __global__ __launch_bounds__(256) void k_secular(const Node* __restrict__ nodes,
     if (thi - tlo <= 2.0 * kEps * fmax(fabs(tlo), fabs(thi))) break;
     t = tn;
   }
-  w.org[lo + i] = (int32_t)o;
-  w.tau[lo + i] = t;
+  if (lane == 0) {
+    w.org[lo + i] = (int32_t)o;
+    w.tau[lo + i] = t;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_zhat(const Node* __restrict__ nodes, int64_t per, Ws w) {
@@ -499,7 +514,8 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
     hipLaunchKernelGGL(k_prep, dim3((unsigned)M), b256, 0, st, nl, n, e, w);
     hipLaunchKernelGGL(k_gather, dim3((unsigned)(M * smax)), b256, 0, st, nl, n, smax, w);
     hipLaunchKernelGGL(k_rotate, dim3((unsigned)(M * per)), b256, 0, st, nl, per, w);
-    hipLaunchKernelGGL(k_secular, dim3((unsigned)(M * per)), b256, 0, st, nl, per, w);
+    const int64_t per4 = (smax + 3) / 4;  // four roots (waves) per workgroup
+    hipLaunchKernelGGL(k_secular, dim3((unsigned)(M * per4)), b256, 0, st, nl, per4, w);
     hipLaunchKernelGGL(k_zhat, dim3((unsigned)(M * per)), b256, 0, st, nl, per, w);
     hipLaunchKernelGGL(k_vec, dim3((unsigned)(M * smax)), b256, 0, st, nl, smax, w);
     hipLaunchKernelGGL(k_compress, dim3((unsigned)(M * smax)), b256, 0, st, nl, smax, w);
