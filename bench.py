@@ -57,6 +57,8 @@ def parse():
                     help="skip the full->band reduction leg")
     ap.add_argument("--no-solve", action="store_true",
                     help="skip the whole-solve leg (every stage of the eigensolver on the device)")
+    ap.add_argument("--no-gen", action="store_true",
+                    help="skip the generalized-problem leg")
     ap.add_argument("--solve-only", action="store_true",
                     help="instead of the benchmark: only the whole-solve leg (for profiling it on "
                          "its own)")
@@ -340,6 +342,43 @@ def solve_leg(args):
             "residual_ratio_sampled": round(res, 4)}
 
 
+def gen_leg(args):
+    """The generalized problem's own steps at the same n, real fp64: the
+    inverted Cholesky factor of a random symmetric positive definite B
+    (n^3/3 + n^3/3 flops: factorisation and triangular inverse), the forward
+    transformation Linv A Linv^H (2 n^3: two triangular products) and the
+    back-transformation Linv^H Q for nev columns (n^2 nev)."""
+    import torch
+    import paper_1811_01277_amd as P
+    dev = torch.device("cuda:0")
+    n, nev = args.n, args.nev
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed + 17)
+    X = torch.randn(n, n, device=dev, dtype=torch.float64, generator=g)
+    B = X @ X.t() / n
+    B.diagonal().add_(1.0)
+    A = (X + X.t()) * 0.5
+    del X
+    q = torch.randn(nev, n, device=dev, dtype=torch.float64, generator=g).t()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.cholesky_inverse(B.t())          # symmetric: the column-major view is B
+    t1 = time.perf_counter()           # (cholesky_inverse synchronises to check info)
+    P.generalized_to_standard(A.t(), B.t())
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    P.generalized_back(q, B.t())
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    del A, B, q
+    torch.cuda.empty_cache()
+    c, f, b = t1 - t0, t2 - t1, t3 - t2
+    return {"workload": f"generalized steps, n={n}, nev={nev}, r64, random SPD B",
+            "cholesky_inverse_s": round(c, 3), "cholesky_inverse_tflops": round(2 * n ** 3 / 3 / c / 1e12, 2),
+            "to_standard_s": round(f, 3), "to_standard_tflops": round(2 * n ** 3 / f / 1e12, 2),
+            "back_s": round(b, 3), "back_tflops": round(n * n * nev / b / 1e12, 2)}
+
+
 def recorded_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE passes (profiles/*_traffic.json), if they were taken
@@ -444,6 +483,8 @@ def main():
         return
     if args.solve_only:
         print(json.dumps({"solve": solve_leg(args)}), flush=True)
+        if not args.no_gen:
+            print(json.dumps({"generalized": gen_leg(args)}), flush=True)
         return
     if args.bt2_only:
         print(json.dumps({"bt2": bt2_leg(args, [args.nev])}), flush=True)
@@ -548,6 +589,8 @@ def main():
         out["f2b"] = f2b_leg(args)
     if not args.no_solve:
         out["solve"] = solve_leg(args)
+    if not args.no_gen:
+        out["generalized"] = gen_leg(args)
         torch.cuda.empty_cache()
     if not args.no_served:
         out["served_stream"] = served_stream(args)

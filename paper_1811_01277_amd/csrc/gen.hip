@@ -1,8 +1,8 @@
 // Generalized Hermitian-definite eigenproblem (C ABI in include/elpa_gen.h;
 // Kus et al., Sec. 2 and Sec. 4 "Generalized EVP problem").
 //
-// Cholesky B = L L^H, blocked right-looking over panels of nb columns:
-//   the diagonal block is factored by one workgroup with the column
+// Cholesky B = L L^H, blocked right-looking over panels of nb = 64 columns:
+//   the diagonal block is factored in LDS by one workgroup with the column
 //   recurrence (a pivot that is not positive is recorded in *info);
 //   the panel below:     B21 <- B21 L11^{-H}  (triangular solve);
 //   the trailing matrix: B22 -= B21 B21^H     (Hermitian rank-nb update of the
@@ -28,7 +28,7 @@ namespace egen {
 
 using ebt::zc;
 
-constexpr int64_t kNb = 256;  // Cholesky panel width
+constexpr int64_t kNb = 64;  // Cholesky panel width (the diagonal block fits in LDS)
 
 __device__ __forceinline__ double re(double a) { return a; }
 __device__ __forceinline__ double re(zc a) { return a.re; }
@@ -54,37 +54,46 @@ __device__ __forceinline__ zc from_re<zc>(double x) { return zc{x, 0.0}; }
 
 __global__ void k_clear_info(int32_t* info) { *info = 0; }
 
-// Factor the diagonal block B[j0:j0+jb, j0:j0+jb] in place (lower triangle),
-// one workgroup, column by column; skipped once *info is set.
+// Factor the diagonal block B[j0:j0+jb, j0:j0+jb] (jb <= kNb) in place, lower
+// triangle, one workgroup, column by column on a copy in LDS; skipped once
+// *info is set.
 template <typename E>
 __global__ __launch_bounds__(256) void k_potrf_diag(E* __restrict__ B, int64_t ldb, int64_t j0,
                                                     int64_t jb, int32_t* __restrict__ info) {
+  __shared__ E sh[kNb][kNb + 1];  // sh[col][row]
   __shared__ int failed;
   const int tid = threadIdx.x;
   if (tid == 0) failed = *info;
+  E* const blk = B + j0 * ldb + j0;
+  for (int64_t e = tid; e < jb * jb; e += blockDim.x) {
+    const int64_t i = e % jb, j = e / jb;
+    if (i >= j) sh[j][i] = blk[j * ldb + i];
+  }
   __syncthreads();
   if (failed) return;
-  E* const blk = B + j0 * ldb + j0;
-  for (int64_t k = 0; k < jb; ++k) {
-    E* const colk = blk + k * ldb;
-    const double d = re(colk[k]);
+  int64_t k = 0;
+  for (; k < jb; ++k) {
+    const double d = re(sh[k][k]);
     if (!(d > 0.0)) {  // uniform: every thread read the same entry
       if (tid == 0) *info = (int32_t)(j0 + k + 1);
-      return;
+      break;
     }
     const double l = sqrt(d);
-    for (int64_t i = k + 1 + tid; i < jb; i += blockDim.x) colk[i] = div_re(colk[i], l);
+    for (int64_t i = k + 1 + tid; i < jb; i += blockDim.x) sh[k][i] = div_re(sh[k][i], l);
     __syncthreads();
-    if (tid == 0) colk[k] = from_re<E>(l);
+    if (tid == 0) sh[k][k] = from_re<E>(l);
     const int64_t r = jb - k - 1;
     for (int64_t e = tid; e < r * r; e += blockDim.x) {
       const int64_t i = e % r, j = e / r;
-      if (i >= j) {
-        E* const dst = blk + (k + 1 + j) * ldb + (k + 1 + i);
-        *dst = fms(*dst, colk[k + 1 + i], conj_(colk[k + 1 + j]));
-      }
+      if (i >= j) sh[k + 1 + j][k + 1 + i] = fms(sh[k + 1 + j][k + 1 + i], sh[k][k + 1 + i],
+                                                 conj_(sh[k][k + 1 + j]));
     }
     __syncthreads();
+  }
+  if (k < jb) return;  // failed: B's contents are unspecified
+  for (int64_t e = tid; e < jb * jb; e += blockDim.x) {
+    const int64_t i = e % jb, j = e / jb;
+    if (i >= j) blk[j * ldb + i] = sh[j][i];
   }
 }
 
