@@ -14,9 +14,9 @@
 // The panel is then mirrored into the rows above (Hermitian storage), and the
 // trailing matrix A22 = A[p+nbw:, p+nbw:] is updated from both sides with the
 // panel's compact-WY product Q = I - V T V^H, T = M^{-1} diag(tau),
-// M = I + diag(tau) striu(V^H V):
-//   A22 <- Q^H A22 = A22 - V diag(conj tau) M^{-H} (V^H A22),
-//   A22 <- A22 Q   = A22 - ((A22 V) M^{-1} diag(tau)) V^H,
+// M = I + diag(tau) striu(V^H V), in the symmetric two-sided form:
+//   X = A22 V T,  Y = T^H (V^H X),  W = X - V Y / 2,
+//   Q^H A22 Q = A22 - V W^H - W V^H   (one product with inner dimension 2k),
 // as GEMMs and triangular solves on the matrix cores (rocBLAS).
 #include <hip/hip_runtime.h>
 
@@ -229,12 +229,12 @@ int run(int64_t n, int64_t b, E* A, int64_t lda, E* V, int64_t ldv, E* tau, hipS
   for (int64_t p = 0; p + b < n; p += b) {
     const int64_t m = n - p - b, k = std::min(b, m);
     part_e = std::max(part_e, (size_t)ebt::ksplit(m, k, k, es) * k * k);
-    part_e = std::max(part_e, (size_t)ebt::ksplit(m, k, m, es) * k * m);
   }
   const size_t off_pn = 0, off_pd = off_pn + al(2 * Gmax * sizeof(double) + 512),
                off_g = off_pd + al((size_t)Gmax * b * es), off_m = off_g + al((size_t)b * b * es),
-               off_w1 = off_m + al((size_t)b * b * es), off_w2 = off_w1 + al((size_t)b * mmax * es),
-               off_part = off_w2 + al((size_t)mmax * b * es), total = off_part + al(part_e * es);
+               off_w1 = off_m + al((size_t)b * b * es),
+               off_w2 = off_w1 + al((size_t)2 * b * mmax * es),
+               off_part = off_w2 + al((size_t)2 * mmax * b * es), total = off_part + al(part_e * es);
   char* ws = nullptr;
   if (hipMallocAsync((void**)&ws, total, st) != hipSuccess) return ELPA_ERR_NOMEM;
   double* pn0 = (double*)(ws + off_pn);
@@ -279,25 +279,37 @@ int run(int64_t n, int64_t b, E* A, int64_t lda, E* V, int64_t ldv, E* tau, hipS
       if (ok)
         hipLaunchKernelGGL(ebt::k_unit_tri<E>, dim3((unsigned)((k * k + 255) / 256)), dim3(256),
                            0, st, (const E*)Gm, tp, k, M);
-      // left: W1 = diag(conj tau) M^{-H} (V^H A22), A22 -= V W1
-      ok = ok && ebt::gemm_adj_splitk<E, S>(h, k, m, m, Vp, ldv, A22, lda,
-                                            ebt::ksplit(m, k, m, es), part, nullptr, W1, st);
-      ok = ok && Blas<E>::trsm(h, rocblas_side_left, C_, k, m, M, k, W1, k) ==
+      // X = A22 V T (T = M^{-1} diag(tau)) into the W half of P = [V | W]
+      E* Pv = W1;
+      E* Pw = W1 + m * k;
+      E* Rw = W2;
+      E* Rv = W2 + m * k;
+      const auto D2D = hipMemcpyDeviceToDevice;
+      ok = ok && hipMemcpy2DAsync(Pv, (size_t)m * es, Vp, (size_t)ldv * es, (size_t)m * es,
+                                  (size_t)k, D2D, st) == hipSuccess;
+      ok = ok && hipMemcpy2DAsync(Rv, (size_t)m * es, Vp, (size_t)ldv * es, (size_t)m * es,
+                                  (size_t)k, D2D, st) == hipSuccess;
+      ok = ok && Blas<E>::gemm(h, N_, N_, m, k, m, S(1), A22, lda, Vp, ldv, S(0), Pw, m) ==
+                     rocblas_status_success;
+      ok = ok && Blas<E>::trsm(h, rocblas_side_right, N_, m, k, M, k, Pw, m) ==
                      rocblas_status_success;
       if (ok)
         hipLaunchKernelGGL(k_scale<E>, dim3((unsigned)std::min<int64_t>((k * m + 255) / 256, 4096)),
-                           dim3(256), 0, st, W1, k, k, m, tp, true);
-      ok = ok && Blas<E>::gemm(h, N_, N_, m, m, k, S(-1), Vp, ldv, W1, k, S(1), A22, lda) ==
-                     rocblas_status_success;
-      // right: W2 = (A22 V) M^{-1} diag(tau), A22 -= W2 V^H
-      ok = ok && Blas<E>::gemm(h, N_, N_, m, k, m, S(1), A22, lda, Vp, ldv, S(0), W2, m) ==
-                     rocblas_status_success;
-      ok = ok && Blas<E>::trsm(h, rocblas_side_right, N_, m, k, M, k, W2, m) ==
+                           dim3(256), 0, st, Pw, m, m, k, tp, false);
+      // Y = T^H V^H X = diag(conj tau) M^{-H} (V^H X), k x k (in Gm)
+      ok = ok && ebt::gemm_adj_splitk<E, S>(h, k, k, m, Vp, ldv, Pw, m, ebt::ksplit(m, k, k, es),
+                                            part, nullptr, Gm, st);
+      ok = ok && Blas<E>::trsm(h, rocblas_side_left, C_, k, k, M, k, Gm, k) ==
                      rocblas_status_success;
       if (ok)
-        hipLaunchKernelGGL(k_scale<E>, dim3((unsigned)std::min<int64_t>((k * m + 255) / 256, 4096)),
-                           dim3(256), 0, st, W2, m, m, k, tp, false);
-      ok = ok && Blas<E>::gemm(h, N_, C_, m, m, k, S(-1), W2, m, Vp, ldv, S(1), A22, lda) ==
+        hipLaunchKernelGGL(k_scale<E>, dim3((unsigned)((k * k + 255) / 256)), dim3(256), 0, st,
+                           Gm, k, k, k, tp, true);
+      // W = X - V Y / 2, so that Q^H A22 Q = A22 - V W^H - W V^H
+      ok = ok && Blas<E>::gemm(h, N_, N_, m, k, k, S(-0.5), Vp, ldv, Gm, k, S(1), Pw, m) ==
+                     rocblas_status_success;
+      ok = ok && hipMemcpyAsync(Rw, Pw, (size_t)m * k * es, D2D, st) == hipSuccess;
+      // A22 -= [V W] [W V]^H: one rank-2k product over both triangles
+      ok = ok && Blas<E>::gemm(h, N_, C_, m, m, 2 * k, S(-1), W1, m, W2, m, S(1), A22, lda) ==
                      rocblas_status_success;
       if (!ok || hipGetLastError() != hipSuccess) rc = ELPA_ERR_DEVICE;
     }
