@@ -228,7 +228,7 @@ def bt2_leg(args, nevs=None):
 def b2t_leg(args):
     """Band -> tridiagonal reduction (elpa_band_to_tridiag) on a random
     symmetric band matrix of the same n, nbw 64, real fp64, drawn on the
-    device.  Latency-bound (about 4 n launches of independent chase steps), so
+    device.  Latency-bound (about 3 n launches of independent chase steps), so
     the figures are time, chase steps per second and time per launch."""
     import torch
     import paper_1811_01277_amd as P
@@ -242,7 +242,7 @@ def b2t_leg(args):
     i = torch.arange(n, device=dev)
     B.masked_fill_((i[:, None] - i[None, :]).abs() > b, 0.0)
     steps = P.num_reflectors(n, b)
-    launches = max(4 * s + -(-(n - 1 - s) // b) for s in range(n - 1))
+    launches = max(3 * s + -(-(n - 1 - s) // b) for s in range(n - 1))
     times = []
     for _ in range(2):
         a = B.clone().t()   # symmetric: the column-major view holds the same matrix
@@ -492,7 +492,7 @@ def main():
         print(json.dumps({"bt2": bt2_leg(args, [args.nev])}), flush=True)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1 "
                                    "(the path shards by columns across GPUs by design, "
                                    "but no multi-GPU run exists)"}))
         sys.exit(2)

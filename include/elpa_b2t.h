@@ -37,8 +37,8 @@ extern "C" {
  * dtype: ELPA_R64 or ELPA_C64 (ELPA_R32 is not provided: single-precision
  *    solves keep the reduction in double precision); 1 <= nbw <= 512.
  * Asynchronous on `stream` (a hipStream_t; NULL = the null stream); about
- * 4 n kernel launches, each a bounded set of independent chase steps (steps
- * whose windows are disjoint), in an order equal to the sequential one.
+ * 3 n kernel launches, each a bounded set of independent chase steps (steps
+ * that touch disjoint entries), in an order equal to the sequential one.
  * Returns ELPA_OK or ELPA_ERR_ARG / _DTYPE / _ALIGN / _DEVICE (elpa_hh.h);
  * arguments are checked before anything is enqueued; n == 1 writes d only.
  */

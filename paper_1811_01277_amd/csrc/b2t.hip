@@ -4,13 +4,15 @@
 // back-transformation.
 //
 // Schedule.  Chase step (s, j) (row r = s+1+j*nbw, length L <= nbw) reads and
-// writes only the square [r-nbw, r+L+nbw) x [r-nbw, r+L+nbw) of the matrix.
-// Step (s+1, j') overlaps a step (s, j'') only for j'' <= j'+3, and two steps
-// of one sweep overlap only when adjacent; so with the launch index
-//   t(s, j) = j + 4 s
-// every overlapping pair runs in launches ordered as in the sequential
-// reduction (sweep by sweep, step by step), and the steps of one launch
-// (same t, distinct s) touch disjoint squares.  One workgroup per step;
+// writes only entries of the square [r-nbw, r+L+nbw)^2 that lie in rows
+// [r, r+L) or in columns [r, r+L).  A step (s+1, j') with j' <= j-3 stays
+// within indices up to r-nbw, and meets index r-nbw only in rows and columns
+// below r, so it shares no entry with (s, j); steps further apart share none
+// either.  So with the launch index
+//   t(s, j) = j + 3 s
+// every pair that shares entries runs in launches ordered as in the
+// sequential reduction (sweep by sweep, step by step), and the steps of one
+// launch (same t, distinct s) touch disjoint entries.  One workgroup per step;
 // kernel boundaries order the launches.  There is no waiting between
 // workgroups.
 //
@@ -72,8 +74,12 @@ __device__ __forceinline__ double wave_sum(double x) {
 __device__ __forceinline__ z64 wave_sum(z64 x) { return z64{wave_sum(x.re), wave_sum(x.im)}; }
 
 constexpr int kMaxNb = 512;
+// Launch t runs the steps (s, t - kLag s): two steps of one launch touch
+// disjoint entries (the later sweep only rows and columns below r - nb, the
+// earlier one only from r on, sharing index r - nb in different entries).
+constexpr int64_t kLag = 3;
 
-// one launch: the steps (s, t - 4 s) for s = s_lo .. s_lo + gridDim.x - 1, one
+// one launch: the steps (s, t - kLag s) for s = s_lo .. s_lo + gridDim.x - 1, one
 // 512-thread workgroup (8 waves) per step
 template <typename E>
 __global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, int64_t n,
@@ -84,7 +90,7 @@ __global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, i
   __shared__ E sh_tau;
   __shared__ double sh_beta;
   const int64_t s = s_lo + blockIdx.x;
-  const int64_t j = t - 4 * s;
+  const int64_t j = t - kLag * s;
   const int64_t r = s + 1 + j * nb;
   const int64_t L = (nb < n - r) ? nb : n - r;
   const int64_t c = (j == 0) ? s : r - nb;
@@ -258,15 +264,15 @@ inline int64_t steps_of(int64_t n, int64_t nb, int64_t s) { return (n - 1 - s + 
 template <typename E>
 int run(int64_t n, int64_t nb, E* A, int64_t lda, double* d, double* e, E* hh, E* tau,
         hipStream_t st) {
-  // launches t = 0 .. T-1 with T = max_s (4 s + J(s)); the active sweeps of
-  // launch t are s_lo(t) .. min(t / 4, n - 2), s_lo the least s with
-  // 4 s + J(s) > t (4 s + J(s) increases with s)
+  // launches t = 0 .. T-1 with T = max_s (3 s + J(s)); the active sweeps of
+  // launch t are s_lo(t) .. min(t / kLag, n - 2), s_lo the least s with
+  // 3 s + J(s) > t (3 s + J(s) increases with s)
   int64_t T = 0;
-  for (int64_t s = 0; s <= n - 2; ++s) T = std::max(T, 4 * s + steps_of(n, nb, s));
+  for (int64_t s = 0; s <= n - 2; ++s) T = std::max(T, kLag * s + steps_of(n, nb, s));
   int64_t s_lo = 0;
   for (int64_t t = 0; t < T; ++t) {
-    while (s_lo <= n - 2 && 4 * s_lo + steps_of(n, nb, s_lo) <= t) ++s_lo;
-    const int64_t s_hi = std::min<int64_t>(t / 4, n - 2);
+    while (s_lo <= n - 2 && kLag * s_lo + steps_of(n, nb, s_lo) <= t) ++s_lo;
+    const int64_t s_hi = std::min<int64_t>(t / kLag, n - 2);
     if (s_hi < s_lo) continue;
     hipLaunchKernelGGL(k_chase<E>, dim3((unsigned)(s_hi - s_lo + 1)), dim3(512), 0, st, A, lda,
                        n, nb, t, s_lo, hh, tau);
