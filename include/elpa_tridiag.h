@@ -21,8 +21,9 @@
  *    directly.  0 <= nev <= n.
  *
  * The call allocates its workspace (about 5 n^2 doubles) in stream order and
- * synchronises `stream` once per level of the merge tree whose merges exceed
- * 256 rows (the host sizes the products from the deflation counts).
+ * synchronises `stream` after uploading the merge tree (n > 1) and once per
+ * level of the tree whose merges exceed 256 rows (the host sizes the
+ * products from the deflation counts).
  * Returns ELPA_OK or ELPA_ERR_ARG / _DTYPE / _ALIGN / _NOMEM / _DEVICE
  * (elpa_hh.h); arguments are checked before anything is enqueued.  n = 0 is
  * a no-op.

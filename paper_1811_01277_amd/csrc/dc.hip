@@ -498,8 +498,10 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
   Node* dnodes = (Node*)take(nodes_b);
 
   int rc = ELPA_OK;
-  if (!flat.empty() && hipMemcpyAsync(dnodes, flat.data(), flat.size() * sizeof(Node),
-                                      hipMemcpyHostToDevice, st) != hipSuccess)
+  // the table lives in host memory owned by this call: wait for the copy
+  if (!flat.empty() && (hipMemcpyAsync(dnodes, flat.data(), flat.size() * sizeof(Node),
+                                       hipMemcpyHostToDevice, st) != hipSuccess ||
+                        hipStreamSynchronize(st) != hipSuccess))
     rc = ELPA_ERR_DEVICE;
   if (rc == ELPA_OK)
     hipLaunchKernelGGL(k_init, dim3(grid_for(n * n)), dim3(256), 0, st, n, d, e, w.L, w.Q);

@@ -170,3 +170,63 @@ def test_whole_solve_on_gpu(torch_dev, cplx):
     assert checks.residual_ratio(A, Z, lam) < 50
     assert checks.orth_ratio(Z) < 50
     assert np.max(np.abs(lam - np.linalg.eigvalsh(A))) <= 8 * n * EPS * np.linalg.norm(A, 2)
+
+
+def test_padded_ldz_through_the_c_abi(torch_dev):
+    """elpa_tridiag_eigh with ldz > n: the eigenvectors land in rows [0, n) of
+    each column and the padding rows are left as they were."""
+    torch, dev = torch_dev
+    import ctypes as C
+    import paper_1811_01277_amd as P
+    n, nev, ldz = 130, 37, 141
+    d, e = make("gauss", n, 901)
+    lam0, Z0 = gpu_solve(torch, dev, d, e)
+    dt = torch.from_numpy(d).to(dev)
+    et = torch.from_numpy(e).to(dev)
+    lam = torch.empty(n, dtype=torch.float64, device=dev)
+    buf = torch.full((nev, ldz), float("nan"), dtype=torch.float64, device=dev)
+    st = torch.cuda.current_stream(dev).cuda_stream
+    rc = P.library().elpa_tridiag_eigh(n, nev, C.c_void_p(dt.data_ptr()), C.c_void_p(et.data_ptr()),
+                                       C.c_void_p(lam.data_ptr()), C.c_void_p(buf.data_ptr()), ldz,
+                                       P.R64, C.c_void_p(st))
+    assert rc == 0
+    torch.cuda.synchronize()
+    got = buf.cpu().numpy().T
+    assert np.array_equal(got[:n], Z0[:, :nev]) and np.array_equal(lam.cpu().numpy(), lam0)
+    assert np.all(np.isnan(got[n:]))
+
+
+def test_whole_solve_full_size(torch_dev):
+    """n = 20000, nbw = 64, nev = 2000, every stage on the device: for sampled
+    eigenpairs of the original matrix the residual ratio
+    ||A z - lambda z||_1 / (||A||_1 n eps) stays below 50, the sampled
+    columns are orthonormal to n eps, and the eigenvalues ascend and lie in
+    the spectrum's bounds (|lambda| <= ||A||_1)."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 20000, 64, 2000
+    g = torch.Generator(device=dev)
+    g.manual_seed(931)
+    A = torch.randn(n, n, device=dev, dtype=torch.float64, generator=g)
+    A = (A + A.t()) * 0.5
+    a = A.clone().t()
+    print("whole solve n=20000", flush=True)
+    v, t1 = P.full_to_band(a, nbw)
+    d, e, hh, tau = P.band_to_tridiag(a, nbw)
+    del a
+    lam, q = P.tridiag_eigh(d, e, nev)
+    P.hh_trafo(q, hh, tau, nbw)
+    P.bt2_trafo(q, v, t1, nbw)
+    del v, t1, hh, tau
+    idx = torch.tensor([0, 1, 500, 1234, nev - 2, nev - 1], device=dev)
+    Z = q[:, idx]
+    R = A @ Z - Z * lam[idx]
+    norm1 = float(A.abs().sum(0).max())
+    res = float(R.abs().sum(0).max()) / (norm1 * n * EPS)
+    G = Z.t() @ Z - torch.eye(len(idx), dtype=torch.float64, device=dev)
+    orth = float(G.abs().sum(0).max()) / (n * EPS)
+    lam_h = lam.cpu().numpy()
+    del A, q, Z, R
+    torch.cuda.empty_cache()
+    assert res < 50 and orth < 50, (res, orth)
+    assert np.all(np.diff(lam_h) >= 0) and np.max(np.abs(lam_h)) <= norm1
