@@ -125,7 +125,7 @@ __global__ __launch_bounds__(kRows) void k_reflect(const E* __restrict__ A, int6
                                                    E* __restrict__ V, int64_t ldv,
                                                    E* __restrict__ tau, E* __restrict__ pd) {
   __shared__ E sh[2];
-  __shared__ E red[4];
+  __shared__ E wred[kRows / 64][kMaxNb];
   if (threadIdx.x == 0) {
     E t, s;
     double beta;
@@ -145,12 +145,22 @@ __global__ __launch_bounds__(kRows) void k_reflect(const E* __restrict__ A, int6
       v = from_re<E>(1.0);
     V[r0 + row + (p + i) * ldv] = v;  // zeros above the unit lead
   }
+  // partial products conj(v)^T A[:, p+j]: every wave reduces all columns with
+  // shuffles (no barrier between columns, so their loads overlap), then the
+  // four waves' sums are added in a fixed order
   const E cv = conj_(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int64_t j = i + 1; j < b; ++j) {
     const E x = (row < m && row >= i) ? Num<E>::mul(cv, A[r0 + row + (p + j) * lda])
                                       : from_re<E>(0.0);
-    const E t = block_sum(x, red);
-    if (threadIdx.x == 0) pd[(int64_t)blockIdx.x * b + j] = t;
+    const E t = wave_sum(x);
+    if (lane == 0) wred[wave][j] = t;
+  }
+  __syncthreads();
+  for (int64_t j = i + 1 + threadIdx.x; j < b; j += blockDim.x) {
+    E t = wred[0][j];
+    for (int w = 1; w < kRows / 64; ++w) t = Num<E>::add(t, wred[w][j]);
+    pd[(int64_t)blockIdx.x * b + j] = t;
   }
 }
 
