@@ -26,7 +26,9 @@
 //             delta_j)/(delta_i - delta_j) prod_{j<=i<K-1} (lambda_i -
 //             delta_j)/(delta_i+1 - delta_j), sign of w_j;
 //   vec:      U[:, i] = w^ / (delta - lambda_i), normalised;
-//   product:  Out = W[:, survivors] U;
+//   product:  Out = W[:, survivors] U; above 256 rows as two products on the
+//             halves, the survivors grouped by the rows they can be nonzero
+//             in (child 1 only, both after a rotation, child 2 only);
 //   final:    every value's rank among the merge's s values; L and Q's block
 //             rewritten in ascending order.
 #include <hip/hip_runtime.h>
@@ -53,8 +55,8 @@ constexpr double kEps = 1.1102230246251565e-16;  // 2^-53
 
 struct Ws {
   double *Q, *L, *Ds, *zs, *delta, *wv, *rc, *rs, *tau, *zh, *vals;
-  int32_t *perm, *ndl, *dfl, *ra, *rb, *org;
-  int32_t *K, *ndf, *nrot;
+  int32_t *perm, *ndl, *dfl, *ra, *rb, *org, *rflag, *gidx;
+  int32_t *K, *ndf, *nrot, *grp;
   double* rho;
   double *Wg, *Qc, *U, *Out;
 };
@@ -130,6 +132,7 @@ __global__ __launch_bounds__(256) void k_prep(const Node* __restrict__ nodes, in
     w.perm[lo + rank] = (int32_t)t;
     w.Ds[lo + rank] = val;
     w.zs[lo + rank] = zv;
+    w.rflag[lo + t] = 0;
     dmax = fmax(dmax, fabs(val));
     zmax = fmax(zmax, fabs(zv));
   }
@@ -169,6 +172,8 @@ __global__ __launch_bounds__(256) void k_prep(const Node* __restrict__ nodes, in
       w.rc[lo + nrot] = c;
       w.rs[lo + nrot] = sn;
       ++nrot;
+      w.rflag[lo + pj] = 1;
+      w.rflag[lo + p] = 1;
       w.dfl[lo + ndf++] = (int32_t)pj;
     } else {
       w.ndl[lo + K] = (int32_t)pj;
@@ -184,6 +189,21 @@ __global__ __launch_bounds__(256) void k_prep(const Node* __restrict__ nodes, in
     w.wv[lo + K] = zpj;
     ++K;
   }
+  // survivors grouped by the rows their column can be nonzero in: child 1
+  // only, both (rotated), child 2 only; gidx = the column of Qc (and row of U)
+  int32_t g[3] = {0, 0, 0};
+  for (int32_t j = 0; j < K; ++j) {
+    const int32_t pos = w.ndl[lo + j];
+    ++g[w.rflag[lo + pos] ? 1 : (w.perm[lo + pos] < s1 ? 0 : 2)];
+  }
+  int32_t c[3] = {0, g[0], g[0] + g[1]};
+  for (int32_t j = 0; j < K; ++j) {
+    const int32_t pos = w.ndl[lo + j];
+    w.gidx[lo + j] = c[w.rflag[lo + pos] ? 1 : (w.perm[lo + pos] < s1 ? 0 : 2)]++;
+  }
+  w.grp[3 * blockIdx.x] = g[0];
+  w.grp[3 * blockIdx.x + 1] = g[1];
+  w.grp[3 * blockIdx.x + 2] = g[2];
   w.K[blockIdx.x] = K;
   w.ndf[blockIdx.x] = ndf;
   w.nrot[blockIdx.x] = nrot;
@@ -310,8 +330,8 @@ __global__ __launch_bounds__(256) void k_zhat(const Node* __restrict__ nodes, in
   w.zh[lo + j] = copysign(sqrt(fmax(pr, 0.0)), w.wv[lo + j]);
 }
 
-// U[:, i] (ld s) = zhat / (delta - lambda_i), normalised; one workgroup per
-// (merge, column).
+// U[gidx[j], i] (ld s) = zhat_j / (delta_j - lambda_i), normalised; one
+// workgroup per (merge, column).
 __global__ __launch_bounds__(256) void k_vec(const Node* __restrict__ nodes, int64_t smax, Ws w) {
   __shared__ double red[4];
   const int64_t m = (int64_t)blockIdx.x / smax, i = (int64_t)blockIdx.x % smax;
@@ -329,10 +349,10 @@ __global__ __launch_bounds__(256) void k_vec(const Node* __restrict__ nodes, int
   const double nrm = sqrt(block_sum(ss, red));
   double* __restrict__ U = w.U + nd.woff + i * s;
   for (int64_t j = threadIdx.x; j < K; j += blockDim.x)
-    U[j] = (w.zh[lo + j] / ((dl[j] - sg) - t)) / nrm;
+    U[w.gidx[lo + j]] = (w.zh[lo + j] / ((dl[j] - sg) - t)) / nrm;
 }
 
-// Qc[:, j] (ld s) = W[:, survivor j]; one workgroup per (merge, column).
+// Qc[:, gidx[j]] (ld s) = W[:, survivor j]; one workgroup per (merge, column).
 __global__ __launch_bounds__(256) void k_compress(const Node* __restrict__ nodes, int64_t smax,
                                                   Ws w) {
   const int64_t m = (int64_t)blockIdx.x / smax, j = (int64_t)blockIdx.x % smax;
@@ -340,8 +360,17 @@ __global__ __launch_bounds__(256) void k_compress(const Node* __restrict__ nodes
   const int64_t lo = nd.lo, s = nd.hi - nd.lo;
   if (j >= w.K[m]) return;
   const double* __restrict__ src = w.Wg + nd.woff + (int64_t)w.ndl[lo + j] * s;
-  double* __restrict__ dst = w.Qc + nd.woff + j * s;
+  double* __restrict__ dst = w.Qc + nd.woff + (int64_t)w.gidx[lo + j] * s;
   for (int64_t r = threadIdx.x; r < s; r += blockDim.x) dst[r] = src[r];
+}
+
+// C[0:rows, 0:cols] = 0 (ld ldc).
+__global__ __launch_bounds__(256) void k_zero(double* __restrict__ C, int64_t ldc, int64_t rows,
+                                              int64_t cols) {
+  const int64_t tot = rows * cols;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < tot;
+       x += (int64_t)gridDim.x * blockDim.x)
+    C[(x / rows) * ldc + x % rows] = 0.0;
 }
 
 // Out = Qc U for merges of at most 256 rows: one workgroup per merge, a
@@ -460,7 +489,8 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
   const size_t nd8 = al((size_t)n * 8), ni4 = al((size_t)n * 4), nm8 = al((size_t)mmax * 8),
                nm4 = al((size_t)mmax * 4), big = al((size_t)wmax * 8),
                nodes_b = al(std::max<size_t>(flat.size(), 1) * sizeof(Node));
-  const size_t total = al((size_t)n * n * 8) + 10 * nd8 + 6 * ni4 + 3 * nm4 + nm8 + 4 * big + nodes_b;
+  const size_t total = al((size_t)n * n * 8) + 10 * nd8 + 8 * ni4 + 3 * nm4 + al((size_t)mmax * 12) + nm8 +
+                       4 * big + nodes_b;
   char* ws = nullptr;
   if (hipMallocAsync((void**)&ws, total, st) != hipSuccess) return ELPA_ERR_NOMEM;
   char* p = ws;
@@ -487,9 +517,12 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
   w.ra = (int32_t*)take(ni4);
   w.rb = (int32_t*)take(ni4);
   w.org = (int32_t*)take(ni4);
+  w.rflag = (int32_t*)take(ni4);
+  w.gidx = (int32_t*)take(ni4);
   w.K = (int32_t*)take(nm4);
   w.ndf = (int32_t*)take(nm4);
   w.nrot = (int32_t*)take(nm4);
+  w.grp = (int32_t*)take(al((size_t)mmax * 12));
   w.rho = (double*)take(nm8);
   w.Wg = (double*)take(big);
   w.Qc = (double*)take(big);
@@ -505,7 +538,7 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
     rc = ELPA_ERR_DEVICE;
   if (rc == ELPA_OK)
     hipLaunchKernelGGL(k_init, dim3(grid_for(n * n)), dim3(256), 0, st, n, d, e, w.L, w.Q);
-  std::vector<int32_t> Kh((size_t)mmax);
+  std::vector<int32_t> Kh((size_t)mmax), Gh(3 * (size_t)mmax);
   for (int l = (int)lv.size() - 1; rc == ELPA_OK && l >= 0; --l) {
     const int64_t M = (int64_t)lv[l].size();
     int64_t smax = 0;
@@ -525,6 +558,8 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
       hipLaunchKernelGGL(k_gemm_small, dim3((unsigned)M), b256, 0, st, nl, w);
     } else {
       if (hipMemcpyAsync(Kh.data(), w.K, (size_t)M * 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+          hipMemcpyAsync(Gh.data(), w.grp, (size_t)M * 12, hipMemcpyDeviceToHost, st) !=
+              hipSuccess ||
           hipStreamSynchronize(st) != hipSuccess) {
         rc = ELPA_ERR_DEVICE;
         break;
@@ -535,14 +570,32 @@ int run(int64_t n, int64_t nev, const double* d, const double* e, double* lam, E
         rc = ELPA_ERR_DEVICE;
         break;
       }
+      // Out[0:s1] = Qc[0:s1, groups 0,1] U[groups 0,1];
+      // Out[s1:s] = Qc[s1:s, groups 1,2] U[groups 1,2]
+      const auto N_ = rocblas_operation_none;
       for (int64_t mi = 0; mi < M && rc == ELPA_OK; ++mi) {
         const Node& x = lv[l][(size_t)mi];
-        const int64_t s = x.hi - x.lo, K = Kh[(size_t)mi];
+        const int64_t s = x.hi - x.lo, s1 = x.mid - x.lo, K = Kh[(size_t)mi];
+        const int64_t g0 = Gh[3 * (size_t)mi], g1 = Gh[3 * (size_t)mi + 1],
+                      g2 = Gh[3 * (size_t)mi + 2];
         if (K == 0) continue;
-        if (ebt::Blas<double>::gemm(h, rocblas_operation_none, rocblas_operation_none, s, K, K,
-                                    1.0, w.Qc + x.woff, s, w.U + x.woff, s, 0.0, w.Out + x.woff,
-                                    s) != rocblas_status_success)
-          rc = ELPA_ERR_DEVICE;
+        const double* Qc = w.Qc + x.woff;
+        const double* U = w.U + x.woff;
+        double* Out = w.Out + x.woff;
+        bool ok = true;
+        if (g0 + g1 > 0)
+          ok = ebt::Blas<double>::gemm(h, N_, N_, s1, K, g0 + g1, 1.0, Qc, s, U, s, 0.0, Out, s) ==
+               rocblas_status_success;
+        else
+          hipLaunchKernelGGL(k_zero, dim3(grid_for(s1 * K)), dim3(256), 0, st, Out, s, s1, K);
+        if (g1 + g2 > 0)
+          ok = ok && ebt::Blas<double>::gemm(h, N_, N_, s - s1, K, g1 + g2, 1.0, Qc + g0 * s + s1,
+                                             s, U + g0, s, 0.0, Out + s1, s) ==
+                         rocblas_status_success;
+        else
+          hipLaunchKernelGGL(k_zero, dim3(grid_for((s - s1) * K)), dim3(256), 0, st, Out + s1, s,
+                             s - s1, K);
+        if (!ok) rc = ELPA_ERR_DEVICE;
       }
     }
     hipLaunchKernelGGL(k_vals, dim3((unsigned)(M * per)), b256, 0, st, nl, per, w);
