@@ -653,3 +653,48 @@ def tridiag_eigh(d, e, nev=None, dtype=None, stream=None):
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
     return lam, z
+
+
+def eigenvectors(a, nev=None, nbw=64, stream=None):
+    """The whole standard eigensolver on the device, the C-ABI stages in
+    order: full -> band (elpa_full_to_band), band -> tridiagonal
+    (elpa_band_to_tridiag), divide and conquer (elpa_tridiag_eigh),
+    tridiagonal -> band (elpa_hh_trafo) and band -> full (elpa_bt2_trafo).
+
+    a: (n, n) column-major device tensor, float64 or complex128, Hermitian in
+       full storage; overwritten (it holds the band matrix afterwards).
+    Returns (lam, z): all n eigenvalues ascending (float64) and the
+    eigenvectors of the nev (default n) smallest as an (n, nev) column-major
+    tensor of a's dtype."""
+    n = a.shape[0]
+    nev = n if nev is None else int(nev)
+    if n <= 1:
+        import torch
+        lam = a.diagonal().real.to(torch.float64).clone() if n else \
+            torch.empty(0, dtype=torch.float64, device=a.device)
+        z = torch.ones((n, nev), dtype=a.dtype, device=a.device)
+        return lam, z
+    b = max(1, min(nbw, n - 1))
+    v, t1 = full_to_band(a, b, stream)
+    d, e, hh, tau = band_to_tridiag(a, b, stream)
+    lam, z = tridiag_eigh(d, e, nev, a.dtype, stream)
+    if nev > 0:
+        hh_trafo(z, hh, tau, b, stream)
+        bt2_trafo(z, v, t1, b, stream=stream)
+    return lam, z
+
+
+def generalized_eigenvectors(a, b, nev=None, nbw=64, is_already_decomposed=False,
+                             stream=None):
+    """A V = B V Lambda on the device (Hermitian A, Hermitian positive
+    definite B).  Unless is_already_decomposed, b is overwritten by the
+    inverse of its Cholesky factor (cholesky_inverse); a later call with the
+    same B passes that b with is_already_decomposed=True and skips the
+    factorisation.  a is overwritten.  Returns (lam, v) as eigenvectors()."""
+    if not is_already_decomposed:
+        cholesky_inverse(b, stream)
+    generalized_to_standard(a, b, stream)
+    lam, z = eigenvectors(a, nev, nbw, stream)
+    if z.shape[1] > 0:
+        generalized_back(z, b, stream)
+    return lam, z

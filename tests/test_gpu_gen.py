@@ -155,3 +155,30 @@ def test_generalized_solve_on_gpu(torch_dev, cplx):
         assert np.max(np.abs(np.conj(V.T) @ B @ V - np.eye(n))) <= 1e-10
         ref = G.generalized_eigh(A, B, nbw)
         assert np.max(np.abs(lam - ref["lam"])) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("cplx", [False, True])
+def test_generalized_eigenvectors_api(torch_dev, cplx):
+    """paper_1811_01277_amd.generalized_eigenvectors, every step on the GPU
+    (the tridiagonal solve included): the first call factors B and leaves
+    the inverted factor in b; the second, with is_already_decomposed=True and
+    another A, reuses it.  A V = B V Lambda, V^H B V = I, eigenvalues as
+    scipy's generalized solver."""
+    torch, dev = torch_dev
+    import scipy.linalg
+    import paper_1811_01277_amd as P
+    n, nbw, nev = 300, 32, 120
+    B = spd(n, 951, cplx)
+    _, b = dev_cm(torch, dev, B)
+    for rep, seed in enumerate((952, 953)):
+        A = W.herm_gaussian(n, seed) if cplx else W.sym_gaussian(n, seed)
+        _, a = dev_cm(torch, dev, A)
+        print(f"generalized_eigenvectors rep={rep} cplx={cplx}", flush=True)
+        lam, v = P.generalized_eigenvectors(a, b, nev, nbw, is_already_decomposed=rep > 0)
+        torch.cuda.synchronize()
+        lam, V = host(lam), host(v)
+        ref = scipy.linalg.eigh(A, B, eigvals_only=True)
+        scale = np.linalg.norm(A, 2) + np.linalg.norm(B, 2) * np.max(np.abs(ref))
+        assert np.max(np.abs(lam - ref)) <= 1e-11 * scale
+        assert np.max(np.abs(A @ V - B @ V * lam[:nev])) <= 1e-11 * scale
+        assert np.max(np.abs(np.conj(V.T) @ B @ V - np.eye(nev))) <= 1e-10

@@ -230,3 +230,23 @@ def test_whole_solve_full_size(torch_dev):
     torch.cuda.empty_cache()
     assert res < 50 and orth < 50, (res, orth)
     assert np.all(np.diff(lam_h) >= 0) and np.max(np.abs(lam_h)) <= norm1
+
+
+@pytest.mark.parametrize("n,nbw,nev,cplx", [(300, 32, 100, False), (300, 32, 300, True),
+                                            (5, 64, 5, False), (1, 64, 1, False)])
+def test_eigenvectors_api(torch_dev, n, nbw, nev, cplx):
+    """paper_1811_01277_amd.eigenvectors: the whole solve in one call (band
+    width clamped to n - 1 for small n): A Z = Z Lambda, Z^H Z = I,
+    eigenvalues as numpy's."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    A = W.herm_gaussian(n, 941) if cplx else W.sym_gaussian(n, 941)
+    a = torch.from_numpy(np.ascontiguousarray(A.T)).to(dev).t()
+    lam, z = P.eigenvectors(a, nev, nbw)
+    torch.cuda.synchronize()
+    lam, Z = lam.cpu().numpy(), z.cpu().numpy()
+    assert Z.shape == (n, nev)
+    ref = np.linalg.eigvalsh(A)
+    assert np.max(np.abs(lam - ref)) <= 8 * n * EPS * max(np.linalg.norm(A, 2), 1e-300)
+    assert checks.norm1(A @ Z - Z * lam[None, :nev]) <= 50 * n * EPS * checks.norm1(A)
+    assert checks.orth_ratio(Z) < 50
