@@ -87,15 +87,17 @@ __global__ __launch_bounds__(kRows) void k_pnorm(const E* __restrict__ A, int64_
   if (threadIdx.x == 0) pn[blockIdx.x] = t;
 }
 
-// larfg of column p+i from the partial norms: every group derives the same
-// (tau, beta, scale)
+// larfg of column p+i from the partial norms, called by a whole wave: the
+// lanes add the partials in a fixed order (lane l takes l, l+64, ...; then a
+// butterfly), so every workgroup derives the same (tau, beta, scale)
 template <typename E>
 __device__ __forceinline__ void larfg_from(const E* __restrict__ A, int64_t lda, int64_t r0,
                                            int64_t p, int64_t i, int G,
                                            const double* __restrict__ pn, E* tau_out,
                                            double* beta_out, E* scale_out) {
-  double sum = 0.0;
-  for (int g = 0; g < G; ++g) sum += pn[g];
+  double part = 0.0;
+  for (int g = (int)(threadIdx.x & 63); g < G; g += 64) part += pn[g];
+  const double sum = wave_sum(part);
   const E alpha = A[r0 + i + (p + i) * lda];
   const double ar = re(alpha), ai = im(alpha);
   if (sum == 0.0 && ai == 0.0) {
@@ -126,13 +128,15 @@ __global__ __launch_bounds__(kRows) void k_reflect(const E* __restrict__ A, int6
                                                    E* __restrict__ tau, E* __restrict__ pd) {
   __shared__ E sh[2];
   __shared__ E wred[kRows / 64][kMaxNb];
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     E t, s;
     double beta;
     larfg_from(A, lda, r0, p, i, G, pn, &t, &beta, &s);
-    sh[0] = t;
-    sh[1] = s;
-    if (blockIdx.x == 0) tau[p + i] = t;
+    if (threadIdx.x == 0) {
+      sh[0] = t;
+      sh[1] = s;
+      if (blockIdx.x == 0) tau[p + i] = t;
+    }
   }
   __syncthreads();
   const E sc = sh[1];
@@ -176,16 +180,20 @@ __global__ __launch_bounds__(kRows) void k_update(E* __restrict__ A, int64_t lda
   __shared__ double shb;
   __shared__ double red[4];
   const E ct = conj_(tau[p + i]);
-  for (int64_t j = i + 1 + threadIdx.x; j < b; j += blockDim.x) {
-    E w = pd[j];
-    for (int g = 1; g < G; ++g) w = Num<E>::add(w, pd[(int64_t)g * b + j]);
-    coef[j] = Num<E>::mul(ct, w);
+  // coef[j] = conj(tau) sum_g pd[g][j]: one wave per column, lanes over the
+  // partials in a fixed order
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t j = i + 1 + wave; j < b; j += kRows / 64) {
+    E w = from_re<E>(0.0);
+    for (int g = lane; g < G; g += 64) w = Num<E>::add(w, pd[(int64_t)g * b + j]);
+    w = wave_sum(w);
+    if (lane == 0) coef[j] = Num<E>::mul(ct, w);
   }
-  if (threadIdx.x == 0) {
+  if (threadIdx.x < 64) {
     E t, s;
     double beta;
     larfg_from(A, lda, r0, p, i, G, pn_in, &t, &beta, &s);
-    shb = beta;
+    if (threadIdx.x == 0) shb = beta;
   }
   __syncthreads();
   const int64_t row = (int64_t)blockIdx.x * kRows + threadIdx.x;
