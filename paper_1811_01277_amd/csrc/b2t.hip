@@ -87,7 +87,7 @@ __global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, i
                                                E* __restrict__ hh, E* __restrict__ tau) {
   __shared__ E v[kMaxNb];
   __shared__ double part[8];
-  __shared__ E sh_tau;
+  __shared__ E sh_tau, sh_sc;
   __shared__ double sh_beta;
   const int64_t s = s_lo + blockIdx.x;
   const int64_t j = t - kLag * s;
@@ -127,26 +127,25 @@ __global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, i
         sh_tau = z64{(bt - ar) / bt, -ai / bt};
       sh_beta = bt;
       part[0] = 1.0;
+      // scale 1 / (alpha - beta)
+      const E den = sub(alpha, from_re<E>(bt));
+      if constexpr (std::is_same<E, double>::value) {
+        sh_sc = 1.0 / den;
+      } else {
+        const double dd = den.re * den.re + den.im * den.im;
+        sh_sc = z64{den.re / dd, -den.im / dd};
+      }
     }
   }
   __syncthreads();
   const E tv = sh_tau;
   const bool act = part[0] != 0.0;
-  if (act) {
-    // scale 1 / (alpha - beta)
-    const E den = sub(v[0], from_re<E>(sh_beta));
-    E sc;
-    if constexpr (std::is_same<E, double>::value) {
-      sc = 1.0 / den;
-    } else {
-      const double dd = den.re * den.re + den.im * den.im;
-      sc = z64{den.re / dd, -den.im / dd};
-    }
-    __syncthreads();
-    for (int64_t i = 1 + tid; i < L; i += blockDim.x) v[i] = mul(v[i], sc);
+  {
+    // v <- (1, x[1:] / (alpha - beta)); with tau = 0 the tail is already zero
+    const E sc = sh_sc;
+    for (int64_t i = tid; i < L; i += blockDim.x)
+      v[i] = (i == 0) ? from_re<E>(1.0) : (act ? mul(v[i], sc) : v[i]);
   }
-  __syncthreads();
-  if (tid == 0) v[0] = from_re<E>(1.0);
   __syncthreads();
 
   if (act) {
