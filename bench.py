@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="target CPU time of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU baseline leg")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the table of every stated configuration")
     ap.add_argument("--no-served", action="store_true", help="skip the served SCF stream leg")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched workload leg")
     ap.add_argument("--no-bt2", action="store_true",
@@ -65,6 +67,9 @@ def parse():
     ap.add_argument("--bt2-only", action="store_true",
                     help="instead of the benchmark: only the band->full leg at --nev "
                          "(for profiling it on its own)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="instead of the benchmark: only the batched workload leg (for profiling "
+                         "it on its own)")
     ap.add_argument("--served-rates", default="120,250",
                     help="Poisson arrival rates of the served stream (requests / s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -128,7 +133,7 @@ def served_stream(args):
             "runs": runs}
 
 
-def batched_workload():
+def batched_workload(quick=False):
     """The batched workload: 256 real fp64 problems, n_i ~ U{200..2000}
     (seed 401), nbw 32, nev = n_i, all back-transforms in one batched call
     (inputs drawn on the device).  Timed with the library's default plan, then
@@ -160,7 +165,15 @@ def batched_workload():
         return ev[0].elapsed_time(ev[1]) / reps
 
     P.tuner_clear()
+    P.profile_enable(True)
     t_default = timed(lambda: P.hh_trafo_batched(probs))
+    pr = P.profile_last()
+    P.profile_enable(False)
+    if quick:
+        return {"workload": "256 real fp64 problems, n ~ U{200..2000}, nbw 32, nev = n, one call",
+                "gflops_default": round(flops / t_default / 1e6, 1),
+                "ms_default": round(t_default, 3), "launches": pr["launches"],
+                "kernel_ms": round(pr["kernel_ms"], 3)}
     t_single = timed(lambda: [P.hh_trafo(q, h, t, nbw) for (q, h, t, nbw) in probs], reps=1)
     # one uniform plan timed over the whole batch
     t0 = time.perf_counter()
@@ -178,11 +191,114 @@ def batched_workload():
     P.tuner_clear()
     return {"workload": "256 real fp64 problems, n ~ U{200..2000}, nbw 32, nev = n, one call",
             "gflops_default": round(flops / t_default / 1e6, 1),
-            "ms_default": round(t_default, 3),
+            "ms_default": round(t_default, 3), "launches_default": pr["launches"],
+            "kernel_ms_default": round(pr["kernel_ms"], 3),
             "gflops_tuned": round(flops / t_tuned / 1e6, 1), "ms_tuned": round(t_tuned, 3),
             "tuned_plan": plan, "tuning_s": round(tune_s, 1),
             "gflops_per_class_single_call_plans": round(flops / t_class / 1e6, 1),
             "gflops_one_call_per_problem": round(flops / t_single / 1e6, 1)}
+
+
+# The stated back-transformation configurations: (label, n, nbw, nev, dtype).
+# Reflectors and eigenvector blocks are drawn on the device with the seeded
+# generators of workload (synthetic reflectors with the bulge chase's slot
+# structure stand in for the oracle's reduction of the stated matrices).
+CONFIGS = [("C1", 512, 32, 512, "r64")] + \
+    [("C2", 8192, 64, e, "r64") for e in (819, 4096, 8192)] + \
+    [("C3", 20000, 64, e, dt) for dt in ("r64", "r32", "c64") for e in (2000, 10000, 20000)]
+
+
+def configs_leg(args):
+    """Every stated configuration timed in the library's default plan: ms per
+    call (median of the timed calls, HIP events on the launch stream, after
+    one untimed call), counted TFLOP/s, the fraction of the dtype's peak, and
+    the max-abs relative error of one call against the fp64 oracle on sampled
+    columns (fp32: the error of the fp32 path against the oracle of the
+    unrounded fp64 inputs, and against the oracle of the rounded inputs, the
+    5e-5 parity bar).  The oracle runs per column in a thread pool while the
+    GPU times the next configurations."""
+    import torch
+    import workload as W
+    import paper_1811_01277_amd as P
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import bt, checks
+    dev = torch.device("cuda:0")
+    pool = ThreadPoolExecutor(max_workers=host_threads())
+    rows, pending = [], []
+    groups = {}
+    for c in CONFIGS:
+        groups.setdefault((c[1], c[2], c[4]), []).append(c)
+    for gi, ((n, nbw, dt), cfgs) in enumerate(groups.items()):
+        cplx = dt == "c64"
+        wide = np.complex128 if cplx else np.float64
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed + 1000 + gi)
+        hh64, tau64 = W.device_reflectors(torch, n, nbw, dev, g, complex_=cplx)
+        Z64 = W.device_block(torch, n, max(c[3] for c in cfgs), dev, g, complex_=cplx)
+        hh_h, tau_h = hh64.cpu().numpy(), tau64.cpu().numpy()
+        if dt == "r32":
+            hh, tau = hh64.float(), tau64.float()
+            hh_r = hh.cpu().numpy().astype(np.float64)
+            tau_r = tau.cpu().numpy().astype(np.float64)
+            del hh64, tau64
+        else:
+            hh, tau = hh64, tau64
+        for (label, _, _, nev, _) in cfgs:
+            print(f"config {label} n={n} nbw={nbw} nev={nev} {dt}", file=sys.stderr, flush=True)
+            Zs = Z64[:, :nev]
+            src = Zs.t().float().t() if dt == "r32" else Zs
+            q = src.t().clone().t()
+            cols = sorted({0, 31, 32, nev // 2, nev - 1})
+            Zc = Zs[:, cols].cpu().numpy()
+            stream = torch.cuda.current_stream(dev)
+            P.hh_trafo(q, hh, tau, nbw, stream=stream)
+            got = q[:, cols].cpu().numpy().astype(wide)
+            reps = 20 if n * n * nev <= 8192 ** 3 else 3
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+            for i in range(reps):
+                ev[2 * i].record(stream)
+                P.hh_trafo(q, hh, tau, nbw, stream=stream)
+                ev[2 * i + 1].record(stream)
+            torch.cuda.synchronize()
+            ms = float(np.median([ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps)]))
+            fl = counted_flops(n, nev, dt)
+            tf = fl / (ms * 1e-3) / 1e12
+            row = {"config": label, "n": n, "nbw": nbw, "nev": nev, "dtype": dt,
+                   "ms": round(ms, 3), "tflops": round(tf, 2),
+                   "frac_peak": round(tf / PEAK_TFLOPS[dt], 4), "peak_tflops": PEAK_TFLOPS[dt],
+                   "calls_timed": reps, "sampled_columns": len(cols)}
+            if dt == "r32":
+                row["frac_fp64_peak"] = round(tf / PEAK_TFLOPS["r64"], 4)
+            rows.append(row)
+
+            def one(hh_, tau_, z, c):
+                return bt.bt_tridiag_to_band(hh_, tau_, z[:, c:c + 1], n, nbw, nthreads=1)
+
+            def err_of(futs, got_):
+                ref = np.concatenate([f.result() for f in futs], axis=1)
+                return float(f"{checks.max_rel_err(got_, ref):.3e}")
+
+            f64 = [pool.submit(one, hh_h, tau_h, Zc, i) for i in range(len(cols))]
+            pending.append((row, "max_rel_err_vs_fp64_oracle", f64, got))
+            if dt == "r32":
+                Zr = Zc.astype(np.float32).astype(np.float64)
+                f32 = [pool.submit(one, hh_r, tau_r, Zr, i) for i in range(len(cols))]
+                pending.append((row, "max_rel_err_vs_oracle_rounded_inputs", f32, got))
+            del q, src, Zs
+        del hh, tau, Z64
+        torch.cuda.empty_cache()
+    for row, key, futs, got in pending:
+        row[key] = err_of(futs, got)
+    pool.shutdown()
+    for row in rows:
+        tol = 5e-5 if row["dtype"] == "r32" else 1e-12
+        key = "max_rel_err_vs_oracle_rounded_inputs" if row["dtype"] == "r32" else \
+            "max_rel_err_vs_fp64_oracle"
+        row["within_parity_bar"] = bool(row[key] <= tol)
+    return {"measure": "default plan; ms = median HIP-event time per call on the launch stream; "
+                       "tflops = counted flops (2 n (n-1) nev real, 8 n (n-1) nev complex) / ms; "
+                       "errors: max |gpu - oracle| / max |oracle| on sampled columns of one call",
+            "rows": rows}
 
 
 def bt2_leg(args, nevs=None):
@@ -428,6 +544,9 @@ def counted_flops(n, nev, dt):
 
 
 def host_threads():
+    """Host threads this process may use: the cores of its CPU affinity mask,
+    capped by OMP_NUM_THREADS when that is set (the host's share for this
+    job)."""
     try:
         c = len(os.sched_getaffinity(0))
     except AttributeError:
@@ -435,7 +554,25 @@ def host_threads():
     env = os.environ.get("OMP_NUM_THREADS")
     if env and env.isdigit():
         c = min(c, int(env))
-    return max(1, min(c, 16))
+    return max(1, c)
+
+
+def host_info():
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = None
+    return {"nproc": os.cpu_count(), "affinity_cores": aff,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS"), "cpu_model": model}
 
 
 def cpu_baseline(args, hh, tau, Z):
@@ -455,10 +592,17 @@ def cpu_baseline(args, hh, tau, Z):
     t0 = time.perf_counter()
     ref = bt.bt_tridiag_to_band(hh, tau, np.asfortranarray(Z[:, :ncols]), n, nbw, nthreads=thr)
     dt = time.perf_counter() - t0
+    # one core: one 8-column block (the oracle's unit of work)
+    t0 = time.perf_counter()
+    bt.bt_tridiag_to_band(hh, tau, np.asfortranarray(Z[:, :8]), n, nbw, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": round(per_col * ncols / dt / 1e9, 3), "unit": "GFLOP/s", "cores": thr,
             "kind": "oracle",
             "sample": f"{ncols} of {Z.shape[1]} columns, all {n}x{n} nbw={nbw} reflectors, "
-                      f"{dt:.1f} s, fp64 C oracle (OpenMP over 8-column blocks)"}, ref
+                      f"{dt:.1f} s, fp64 C oracle (OpenMP over 8-column blocks)",
+            "one_core": {"value": round(per_col * 8 / dt1 / 1e9, 3), "unit": "GFLOP/s",
+                         "sample": f"8 of {Z.shape[1]} columns, {dt1:.1f} s, 1 thread"},
+            "host": host_info()}, ref
 
 
 def accuracy(gpu_cols, ref, dt):
@@ -487,6 +631,9 @@ def main():
         print(json.dumps({"solve": solve_leg(args)}), flush=True)
         if not args.no_gen:
             print(json.dumps({"generalized": gen_leg(args)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched_workload": batched_workload(quick=True)}), flush=True)
         return
     if args.bt2_only:
         print(json.dumps({"bt2": bt2_leg(args, [args.nev])}), flush=True)
@@ -558,7 +705,10 @@ def main():
                                f"{dt}, synthetic reflectors", "n": n, "nbw": nbw, "nev": nev,
                    "plan": {"path": prof["path"], "k": prof["k"], "tile_steps": prof["steps"],
                             "streams": prof["streams"]}},
-        "pct_fp64_peak": round(100.0 * achieved / PEAK_TFLOPS["r64"], 2),
+        # the headline fraction from the same whole-call time as value; the
+        # dominant kernel's own rate is roofline.achieved
+        "pct_peak_whole_call": round(100.0 * value / 1e3 / peak, 2),
+        "peak_tflops": peak,
         "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None if traffic is None else round(traffic),
@@ -579,6 +729,9 @@ def main():
         gpu_cols = q[:, :min(nev, 4096)].cpu().numpy()
     del q, h, t
     torch.cuda.empty_cache()
+    if not args.no_configs:
+        out["configs"] = configs_leg(args)
+        torch.cuda.empty_cache()
     if not args.no_batched:
         out["batched_workload"] = batched_workload()
         torch.cuda.empty_cache()

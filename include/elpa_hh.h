@@ -36,9 +36,14 @@
  * executed the work.  Calls on different streams are independent and
  * thread-safe.
  *
- * Errors: every argument is validated before anything is enqueued; on an
- * error nothing is enqueued and Q is untouched.  n <= 1 or nev == 0 is a
- * valid no-op (returns ELPA_OK without touching any pointer).
+ * Errors: every call returns a status code, the counterpart of the error
+ * out-argument that every call of the paper's C interface takes (Sec. 4.1,
+ * the example use of the C interface); ELPA_OK = 0 is success.  Every
+ * argument is validated before anything is enqueued; on an error nothing is
+ * enqueued and Q is untouched.  n <= 1 or nev == 0 is a valid no-op (returns
+ * ELPA_OK without touching any pointer).  A workspace that cannot be
+ * allocated (more than the device holds, or the allocator refuses) returns
+ * ELPA_ERR_NOMEM with nothing enqueued.
  */
 #ifndef ELPA_HH_H
 #define ELPA_HH_H
@@ -52,15 +57,16 @@ extern "C" {
 /* element types */
 enum { ELPA_R64 = 0, ELPA_R32 = 1, ELPA_C64 = 2 };
 
-/* return codes */
+/* return codes (the paper's C interface reports errors through an error
+   argument of every call, Sec. 4.1; here the return value carries them) */
 enum {
     ELPA_OK = 0,
     ELPA_ERR_ARG = -1,    /* bad size, ldq < n, nbw < 1, null pointer */
     ELPA_ERR_DTYPE = -2,  /* unknown element type */
     ELPA_ERR_ALIGN = -3,  /* pointer not aligned to the element size */
-    ELPA_ERR_NOMEM = -4,  /* device workspace could not be allocated */
+    ELPA_ERR_NOMEM = -4,  /* device workspace could not be allocated (nothing enqueued) */
     ELPA_ERR_DEVICE = -5, /* HIP launch or runtime failure */
-    ELPA_ERR_PLAN = -6    /* explicit plan not valid for this problem */
+    ELPA_ERR_PLAN = -6    /* explicit plan not valid for this problem (or a field out of range) */
 };
 
 /* kernel family selection */
@@ -97,8 +103,9 @@ enum {
  * column groups) are split into this many groups whose launch sequences run
  * on concurrent library-owned streams, forked from and joined back into the
  * caller's stream (1 = everything on the caller's stream; at most 8;
- * 0 = library choice, 2).
- * Results do not depend on order or streams.
+ * 0 = library choice, 2); batch: schedule of the two-lane kernel in batched
+ * calls, ELPA_BATCH_* (single-problem calls ignore it).
+ * Results do not depend on order, streams or batch.
  */
 typedef struct {
     int32_t path;
@@ -106,8 +113,16 @@ typedef struct {
     int32_t steps;
     int32_t order;
     int32_t streams;
-    int32_t reserved;   /* must be 0 */
+    int32_t batch;
 } elpa_hh_plan;
+
+/* schedule of a batched call's two-lane group (elpa_hh_plan.batch) */
+enum {
+    ELPA_BATCH_AUTO = 0,       /* the one with the smaller modelled time (see
+                                  elpa_hh_trafo_batched) */
+    ELPA_BATCH_ONE_LAUNCH = 1, /* every (problem, stripe) unit in one launch */
+    ELPA_BATCH_DIAGONAL = 2    /* every problem's diagonal launch sequence side by side */
+};
 
 /*
  * Number of reflector slots N_refl = sum_s J(s) of an n x n band matrix of
@@ -156,13 +171,31 @@ typedef struct {
 /*
  * Batched back-transformation: the same operation for every problem in
  * probs[0..count) (host array, read before the call returns), asynchronous on
- * `stream`.  Problems may differ in n, nev and ldq; problems that share
- * (dtype, nbw) and have a compiled stripe kernel run together in one
- * persistent launch (one launch per such group, in order on the stream), the
- * others through the reference kernel one by one.  Every problem is validated
+ * `stream`.  Problems may differ in n, nev and ldq.  Problems that share
+ * (dtype, nbw) and run the two-lane stripe kernel (ELPA_PATH_SPLIT, the
+ * default where one is compiled) run as one group, in one of two schedules:
+ *   - ONE kernel launch: every workgroup carries one 32-column stripe of one
+ *     problem through all of that problem's reflectors (sweep blocks
+ *     descending, chase steps ascending), the problems ordered by decreasing
+ *     work so that the longest stripes start first; no workgroup waits for
+ *     another.  For batches of many problems, whose stripes fill the device.
+ *   - the diagonal launch sequence of every problem side by side (launch t
+ *     runs launch t's tiles of every problem): for a few large problems,
+ *     whose stripes alone would leave the device idle.
+ * plan->batch picks one (ELPA_BATCH_*); by default the library models both
+ * (resident wave slots, per-unit and per-launch work) and runs the faster,
+ * the single launch unless it is modelled more than 10 % slower; an explicit
+ * plan->steps selects the diagonal sequence.  A reflector-packing launch and
+ * a layout-conversion launch run before and one conversion launch after,
+ * each over all problems of the group.  Problems whose plan picks the
+ * one-lane or compact-WY family run as that family's diagonal launch
+ * sequence (all problems of the group side by side, one launch per diagonal);
+ * problems without a compiled stripe kernel run through the reference kernel
+ * one by one.  Groups run in order on the stream.  Every problem is validated
  * first; if any is invalid nothing is enqueued and the code of the first
  * invalid problem is returned.  The Q buffers of different problems must not
- * overlap.  plan may be NULL (library choice) and applies to every group.
+ * overlap.  plan may be NULL (library choice) and applies to every group
+ * (one launch needs one compiled kernel, so k is uniform within a group).
  */
 int elpa_hh_trafo_batched(const elpa_hh_problem *probs, int64_t count, void *stream,
                           const elpa_hh_plan *plan);
@@ -248,7 +281,9 @@ int elpa_hh_tune(int64_t n, int64_t nev, int64_t nbw, const void *hh, const void
 
 /*
  * Batch tuner: times uniform plans (one plan for every problem, among those
- * that every problem of the batch can run in a batched call) on scratch
+ * that every problem of the batch can run in a batched call; for the two-lane
+ * family both batched schedules, ELPA_BATCH_ONE_LAUNCH and
+ * ELPA_BATCH_DIAGONAL) on scratch
  * copies of the problems' Q (the Q buffers are not modified; the call
  * allocates the sum of the spans ldq*(nev-1)+n and waits for `stream`) and
  * returns the fastest in *best, to be passed to elpa_hh_trafo_batched.  The

@@ -63,7 +63,7 @@ def jacobi_eigh(A, sweeps=60, tol=None):
                 if abs(apq) <= 1e-300:
                     continue
                 theta = (A[q, q] - A[p, p]) / (2.0 * apq)
-                t = (1.0 if theta >= 0 else -1.0) / (abs(theta) + np.sqrt(theta * theta + 1.0))
+                t = (1.0 if theta >= 0 else -1.0) / (abs(theta) + np.hypot(theta, 1.0))
                 c = 1.0 / np.sqrt(t * t + 1.0)
                 s = t * c
                 for k in range(n):

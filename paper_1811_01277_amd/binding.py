@@ -8,6 +8,7 @@ _LIB_NAME = "libelpahip.so"
 R64, R32, C64 = 0, 1, 2
 PATH_AUTO, PATH_REF, PATH_STRIPE, PATH_SPLIT, PATH_WY = 0, 1, 2, 3, 4
 ORDER_AUTO, ORDER_LINEAR, ORDER_XCD = 0, 1, 2
+BATCH_AUTO, BATCH_ONE_LAUNCH, BATCH_DIAGONAL = 0, 1, 2
 
 _lib = None
 
@@ -20,7 +21,7 @@ class ElpaError(RuntimeError):
 
 class _Plan(C.Structure):
     _fields_ = [("path", C.c_int32), ("k", C.c_int32), ("steps", C.c_int32),
-                ("order", C.c_int32), ("streams", C.c_int32), ("reserved", C.c_int32)]
+                ("order", C.c_int32), ("streams", C.c_int32), ("batch", C.c_int32)]
 
 
 class _Problem(C.Structure):
@@ -145,7 +146,8 @@ def profile_last():
 
 
 def _plan_dict(p):
-    return {"path": p.path, "k": p.k, "steps": p.steps, "order": p.order, "streams": p.streams}
+    return {"path": p.path, "k": p.k, "steps": p.steps, "order": p.order, "streams": p.streams,
+            "batch": p.batch}
 
 
 def _check(rc):
@@ -216,11 +218,11 @@ def slot_offset(n, nbw, s):
     return int(library().elpa_hh_slot_offset(n, nbw, s))
 
 
-def _plan(path, k, steps=0, order=0, streams=0):
-    if path is None and not k and not steps and not order and not streams:
+def _plan(path, k, steps=0, order=0, streams=0, batch=0):
+    if path is None and not k and not steps and not order and not streams and not batch:
         return None
     return _Plan(int(path or 0), int(k or 0), int(steps or 0), int(order or 0),
-                 int(streams or 0), 0)
+                 int(streams or 0), int(batch or 0))
 
 
 def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
@@ -263,7 +265,8 @@ def _dtype_code(t):
     return m[t.dtype]
 
 
-def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0, order=0, streams=0):
+def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0, order=0, streams=0,
+             batch=0):
     """Q <- H(0,0) ... H(n-2,J-1) Q in place on a column-major torch tensor.
 
     q:   (n, nev) device tensor with q.stride(0) == 1 (column major, ldq =
@@ -272,7 +275,8 @@ def hh_trafo(q, hh, tau, nbw, stream=None, path=None, k=0, steps=0, order=0, str
     tau: 1-D contiguous tensor of N_refl scalars (same dtype).
     stream: torch.cuda.Stream or raw hipStream_t int; default: current stream.
     path, k, steps, order, streams: explicit plan (elpa_hh_plan); 0 / None =
-    library choice.
+    library choice.  batch: the batched-schedule field of a plan (accepted so
+    that a tuned plan dict can be passed; a single call ignores it).
     """
     import torch
     if q.dim() != 2:
@@ -332,15 +336,32 @@ def _marshal_batch(problems, stream):
     return arr, st
 
 
-def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, streams=0):
+def hh_trafo_batched_ptr(problems, stream=0, path=None, k=0, steps=0, order=0, streams=0,
+                         batch=0):
+    """Raw-pointer batched entry over (n, nev, nbw, ldq, hh, tau, q, dtype code)
+    tuples: returns the library's status code (no raise)."""
+    arr = (_Problem * max(1, len(problems)))()
+    for i, (n, nev, nbw, ldq, hh, tau, q, dt) in enumerate(problems):
+        arr[i] = _Problem(n, nev, nbw, ldq, hh, tau, q, dt, 0)
+    pl = _plan(path, k, steps, order, streams, batch)
+    return int(library().elpa_hh_trafo_batched(arr, len(problems), C.c_void_p(stream),
+                                                C.byref(pl) if pl is not None else None))
+
+
+def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, streams=0,
+                     batch=0):
     """Batched Q <- H ... H Q over a list of (q, hh, tau, nbw) tensor tuples.
 
     Each q is a column-major (n, nev) device tensor as in hh_trafo; problems
-    may differ in n, nev and dtype.  One persistent launch per (dtype, nbw)
-    group on one stream.
+    may differ in n, nev and dtype.  The problems of one (dtype, nbw) group
+    that run the two-lane kernel are back-transformed in one kernel launch
+    (one workgroup per 32-column stripe of a problem, largest problems first);
+    groups run in order on one stream.  batch: BATCH_ONE_LAUNCH or
+    BATCH_DIAGONAL forces that schedule of the two-lane kernel (default: the
+    library's model picks).
     """
     arr, st = _marshal_batch(problems, stream)
-    pl = _plan(path, k, steps, order, streams)
+    pl = _plan(path, k, steps, order, streams, batch)
     rc = int(library().elpa_hh_trafo_batched(arr, len(problems), C.c_void_p(st),
                                               C.byref(pl) if pl is not None else None))
     if rc != 0:

@@ -12,8 +12,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libelpahip.so")
-SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_split.hip", "hh_wy.hip", "bt2.hip",
-           "b2t.hip", "f2b.hip", "gen.hip", "dc.hip"]
+# the stripe kernel families are split by element type so that their many
+# fully unrolled variants compile in parallel
+SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_stripe_r64.hip",
+           "hh_stripe_r32.hip", "hh_stripe_c64.hip", "hh_split.hip", "hh_split_r64.hip",
+           "hh_split_r32.hip", "hh_split_c64.hip", "hh_wy.hip", "bt2.hip", "b2t.hip", "f2b.hip",
+           "gen.hip", "dc.hip"]
 ARCH = os.environ.get("ELPA_HIP_ARCH", "gfx950")
 
 FLAGS = [

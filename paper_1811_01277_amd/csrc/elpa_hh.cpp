@@ -70,7 +70,8 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
                                 int* rc, bool batched = false) {
   *rc = ELPA_OK;
   if (plan && (plan->order < ELPA_ORDER_AUTO || plan->order > ELPA_ORDER_XCD ||
-               plan->streams < 0 || plan->streams > 8 || plan->reserved != 0)) {
+               plan->streams < 0 || plan->streams > 8 || plan->batch < ELPA_BATCH_AUTO ||
+               plan->batch > ELPA_BATCH_DIAGONAL)) {
     *rc = ELPA_ERR_PLAN;
     return nullptr;
   }
@@ -135,7 +136,8 @@ int device_cus() {
 const elpa_hh_plan* effective_plan(int32_t dtype, int64_t nbw, int64_t n, int64_t nev,
                                    const elpa_hh_plan* plan, elpa_hh_plan* buf) {
   const bool automatic = !plan || (plan->path == ELPA_PATH_AUTO && plan->k == 0 &&
-                                   plan->steps == 0 && plan->order == 0 && plan->streams == 0);
+                                   plan->steps == 0 && plan->order == 0 && plan->streams == 0 &&
+                                   plan->batch == 0);
   if (automatic && ehh::tuner_lookup(dtype, nbw, n, nev, buf)) return buf;
   return plan;
 }
@@ -147,7 +149,13 @@ ehh::TileOpts tile_opts(const elpa_hh_plan* plan) {
   o.xcd = (plan && plan->order == ELPA_ORDER_XCD) ? 8 : 1;
   // two stripe groups by default: one group's launch tails overlap the other's
   o.streams = (plan && plan->streams > 0) ? plan->streams : 2;
+  o.batch = plan ? plan->batch : ELPA_BATCH_AUTO;
   return o;
+}
+
+// Status code of a launcher's HIP result.
+int status_of(hipError_t e) {
+  return e == hipSuccess ? ELPA_OK : (e == hipErrorOutOfMemory ? ELPA_ERR_NOMEM : ELPA_ERR_DEVICE);
 }
 
 bool aligned(const void* p, int64_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -231,7 +239,7 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
     err = ehh::ref_launcher(dtype)(hh, tau, Q, ldq, n, nev, nbw, st);
     prof.after(st);
   }
-  return err == hipSuccess ? ELPA_OK : ELPA_ERR_DEVICE;
+  return status_of(err);
 }
 
 int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* stream,
@@ -275,7 +283,7 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
     const std::vector<int64_t>& ids = groups[se];
     const hipError_t err = se->batched(probs, ids.data(), (int64_t)ids.size(),
                                        tile_opts(plan), st, cus);
-    if (err != hipSuccess) return ELPA_ERR_DEVICE;
+    if (err != hipSuccess) return status_of(err);
   }
   for (int64_t i : singles) {
     const elpa_hh_problem& p = probs[i];
@@ -284,7 +292,7 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
     const hipError_t err =
         ehh::ref_launcher(p.dtype)(p.hh, p.tau, p.Q, p.ldq, p.n, p.nev, p.nbw, st);
     prof.after(st);
-    if (err != hipSuccess) return ELPA_ERR_DEVICE;
+    if (err != hipSuccess) return status_of(err);
   }
   return ELPA_OK;
 }

@@ -20,6 +20,52 @@ __host__ __device__ __forceinline__ int64_t slot_offset(int64_t n, int64_t b, in
   return csum(n - 1, b) - csum(n - 1 - s, b);
 }
 
+// F(N, d, a, c) = sum_{i=0}^{N-1} floor((a i + c) / d) for a, c >= 0, d > 0,
+// by the Euclid-like reduction of lattice-point counts: whole multiples of d
+// in a and c contribute in closed form; with a, c < d the count of points
+// under the line y = (a x + c)/d, x < N, equals the count under the
+// transposed line with the roles of a and d exchanged, over
+// floor((a N + c)/d) columns.  O(log d) iterations.
+__host__ __device__ __forceinline__ int64_t floor_sum(int64_t N, int64_t d, int64_t a,
+                                                     int64_t c) {
+  int64_t s = 0;
+  while (N > 0) {
+    if (a >= d) {
+      s += (a / d) * (N * (N - 1) / 2);
+      a %= d;
+    }
+    if (c >= d) {
+      s += (c / d) * N;
+      c %= d;
+    }
+    const int64_t top = a * N + c;
+    if (top < d) break;
+    N = top / d;
+    c = top % d;
+    const int64_t t = d;
+    d = a;
+    a = t;
+  }
+  return s;
+}
+
+// Chase steps of sweep block m (sweeps [mK, mK+K)): J0(m) = ceil((n-1-mK)/b),
+// the steps of its first (longest) sweep.
+__host__ __device__ __forceinline__ int64_t block_steps(int64_t n, int64_t b, int64_t K,
+                                                       int64_t m) {
+  return (n - 1 - m * K + b - 1) / b;
+}
+
+// sum_{m' < m} J0(m'): the first packed step record of block m when the
+// records of every block's existing steps are stored back to back (0 <= m <=
+// M = ceil((n-1)/K); m = M gives the total).  With i = m-1-m' the terms are
+// floor((K i + n-2+b-(m-1)K) / b), whose offset is >= b-1 for m <= M.
+__host__ __device__ __forceinline__ int64_t block_base(int64_t n, int64_t b, int64_t K,
+                                                      int64_t m) {
+  if (m <= 0) return 0;
+  return floor_sum(m, b, K, n - 2 + b - (m - 1) * K);
+}
+
 struct z64 {
   double re, im;
 };

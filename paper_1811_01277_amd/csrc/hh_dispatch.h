@@ -19,6 +19,7 @@ struct TileOpts {
   int64_t steps;
   int xcd;
   int streams;
+  int batch;  // ELPA_BATCH_* (batched calls of the two-lane kernel)
 };
 
 using StripeLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
@@ -28,6 +29,11 @@ using BatchedLaunch = hipError_t (*)(const elpa_hh_problem* probs, const int64_t
                                      int64_t cnt, TileOpts opt, hipStream_t st, int num_cu);
 // Device workspace one problem's call allocates (bytes).
 using WorkspaceFn = size_t (*)(int64_t n, int64_t nev);
+// Same as StripeLaunch on a caller-provided device workspace of at least
+// WorkspaceFn(n, nev) bytes (nothing allocated or freed).
+using StripeLaunchWs = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
+                                      int64_t n, int64_t nev, TileOpts opt, hipStream_t st,
+                                      int num_cu, void* ws);
 using RefLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
                                  int64_t n, int64_t nev, int64_t nb, hipStream_t st);
 
@@ -40,6 +46,7 @@ struct StripeEntry {
   StripeLaunch fn;
   BatchedLaunch batched;  // null: no batched form
   WorkspaceFn workspace;
+  StripeLaunchWs with_ws;  // null: the family has no caller-workspace form
 };
 
 const StripeEntry* stripe_table(int* size);  // one lane per column

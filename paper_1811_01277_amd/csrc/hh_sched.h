@@ -32,7 +32,10 @@ struct ProblemDesc {
   int GT;      // 64-column conversion tiles per row band, ceil(nev/64)
   int ptile0;     // first reflector-packing group of this problem (split path)
   const void* P;  // packed reflectors (split path), else null
-  int64_t Jmax;   // chase steps of the packed layout (split path)
+  int64_t Jmax;   // chase steps of the longest sweep, ceil((n-1)/nbw)
+  int unit0;      // first workgroup of this problem in a one-launch batched call
+  int pad_;
+  const void* Bt;  // first packed step record of each sweep block (split path)
 };
 
 // One launch's share of one problem in the batched diagonal schedule:
@@ -115,6 +118,30 @@ __device__ __forceinline__ int zero_after(z64 d) { return zero_after(d.re); }
 
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
+// Stream-ordered workspace allocation on the current device.  A request above
+// the device's total memory fails at once with hipErrorOutOfMemory, without
+// asking the allocator; a failed allocation leaves no error behind for the
+// next runtime call to report.
+inline hipError_t ws_alloc(void** p, size_t bytes, hipStream_t st) {
+  static std::mutex mu;
+  static std::vector<size_t> total;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  {
+    std::lock_guard<std::mutex> g(mu);
+    if ((size_t)dev >= total.size()) total.resize((size_t)dev + 1, 0);
+    if (total[(size_t)dev] == 0) {
+      size_t t = 0;
+      if (hipDeviceTotalMem(&t, dev) == hipSuccess) total[(size_t)dev] = t;
+    }
+    if (total[(size_t)dev] != 0 && bytes > total[(size_t)dev]) return hipErrorOutOfMemory;
+  }
+  e = hipMallocAsync(p, bytes, st);
+  if (e != hipSuccess) (void)hipGetLastError();
+  return e;
+}
+
 // Stream-ordered host->device upload of small host tables.  hipMemcpyAsync
 // from pageable memory copies at call time, but a destination obtained from
 // hipMallocAsync is only valid in stream order (earlier work on the stream may
@@ -174,12 +201,15 @@ class PinnedStaging {
 };
 
 // Fork/join of a launch sequence over internal streams.  With ns == 1 the
-// caller's stream is used directly.  Otherwise ns library streams of the
-// current device (created once, default priority, non-blocking) wait for an
-// event recorded on the caller's stream, and join() makes the caller's stream
-// wait for events recorded behind the work enqueued on them.  The device's
-// pool is locked from fork to join so that concurrent callers do not
-// interleave their fork/join events.
+// caller's stream is used directly.  Otherwise ns library streams (created
+// once, default priority, non-blocking) wait for an event recorded on the
+// caller's stream, and join() makes the caller's stream wait for events
+// recorded behind the work enqueued on them.  Each (device, caller stream)
+// pair has a pool of its own, so calls on different caller streams fork onto
+// different library streams and run concurrently; a pool is locked from fork
+// to join so that concurrent callers on the same stream do not interleave
+// their fork/join events.  Past kMaxPools caller streams on a device, the
+// further ones share one overflow pool.
 class StreamFork {
  public:
   static constexpr int kMax = 8;
@@ -190,7 +220,7 @@ class StreamFork {
     int dev = 0;
     err_ = hipGetDevice(&dev);
     if (err_ != hipSuccess) return;
-    pool_ = &Pool::for_device(dev);
+    pool_ = &Pool::for_stream(dev, caller);
     lock_ = std::unique_lock<std::mutex>(pool_->mu);
     err_ = pool_->ensure(ns_);
     if (err_ != hipSuccess) return;
@@ -240,16 +270,28 @@ class StreamFork {
       }
       return hipSuccess;
     }
-    static Pool& for_device(int dev) {
+    static Pool& for_stream(int dev, hipStream_t caller) {
+      struct Entry {
+        int dev;
+        hipStream_t caller;
+        Pool* pool;
+      };
       static std::mutex mu;
-      static std::vector<Pool*> pools;
+      static std::vector<Entry> pools;
       std::lock_guard<std::mutex> g(mu);
-      if (dev < 0) dev = 0;
-      if ((size_t)dev >= pools.size()) pools.resize((size_t)dev + 1, nullptr);
-      if (!pools[(size_t)dev]) pools[(size_t)dev] = new Pool();
-      return *pools[(size_t)dev];
+      for (const Entry& e : pools)
+        if (e.dev == dev && e.caller == caller) return *e.pool;
+      int on_dev = 0;
+      for (const Entry& e : pools) on_dev += e.dev == dev;
+      // the overflow pool of a device is keyed by an impossible stream value
+      hipStream_t key = on_dev < kMaxPools ? caller : reinterpret_cast<hipStream_t>(~uintptr_t(0));
+      for (const Entry& e : pools)
+        if (e.dev == dev && e.caller == key) return *e.pool;
+      pools.push_back(Entry{dev, key, new Pool()});
+      return *pools.back().pool;
     }
   };
+  static constexpr int kMaxPools = 16;
 
   hipStream_t caller_;
   int ns_;

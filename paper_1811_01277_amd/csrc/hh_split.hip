@@ -1,669 +1,27 @@
-// Split-window stripe kernel (real and complex fp64) of the tridiagonal->band eigenvector
-// back-transformation  Q <- H(0,0) H(0,1) ... H(n-2, J-1) Q  (Kus et al.,
-// Sec. 2 and Sec. 3.1).
-//
-// Same block/step structure and diagonal launch schedule as the one-lane
-// stripe kernel (blocks of K sweeps slide a window of W = NB+K-1 rows down a
-// stripe, one chase step at a time; launch t runs every tile (stripe c, block
-// m, group q of S steps) with (M-1-m)+q = t), with three differences:
-//
-// 1. Two lanes per column.  A wave covers 32 columns; lane l = 32h + c holds
-//    the window rows of parity h of column c.  A lane keeps R = (NB+K)/2
-//    registers instead of NB+K-1, so K (the reuse of every loaded row, the
-//    kernel's arithmetic intensity is K/4 flop per byte) can be about twice
-//    as large for the same register budget, and the unrolled step body is half
-//    as long per reflector (it has to stay inside the instruction cache).
-//    Reflector o of a step (window rows o..o+NB-1) meets, in each lane half,
-//    the registers p = o/2 .. o/2+NB/2-1 (even o) or (o-1)/2 .. (o-1)/2+NB/2
-//    (odd o: one more register, whose reflector value is zero in one half).
-//    The two halves' partial dot products are combined with a lane swap
-//    across the halves (v_permlane32_swap), identically in both halves.
-//    Real reflectors are applied in pairs (odd o, then o-1), which start on
-//    the same register: two dot products in one pass, a 2x2 triangular
-//    correction with the pair coupling, and one update pass, as the paper's
-//    CPU kernels fuse two or more reflectors (Sec. 3.1).
-// 2. Packed reflectors.  A pre-pass writes, for every (block m, step j,
-//    offset o), the reflector (m*K+o, j) in the order the lanes consume it:
-//    per lane half HN+1 values (index 2t+h-(o&1) of v, zero outside [0, L)),
-//    tau in the first half's spare slot, for real records of even o the pair
-//    coupling v(o).v(o+1) in the second half's, zeros for reflectors that do
-//    not exist.  The step body then needs no slot arithmetic and no branches.
-// 3. Stripes are 32 columns wide; a stripe row pair (rows 2p, 2p+1) is one
-//    contiguous 512-byte access of the wave.
-//
-// The extra window row (W is odd, the register file holds W+1 rows) is
-// loaded but never written; it lies one row short of the next block's tile
-// in the same launch.
-#include "hh_common.h"
+// Table of the two-lane stripe kernel instances of every element type
+// (hh_split_r64.hip, hh_split_r32.hip, hh_split_c64.hip), concatenated once.
+#include <vector>
+
 #include "hh_dispatch.h"
-#include "hh_dpp.h"
-#include "hh_sched.h"
 
 namespace ehh {
 
-template <int NB, int K>
-struct SplitGeom {
-  static_assert(NB == 32 || NB == 64, "split kernel supports NB = 32, 64");
-  static_assert(K >= 2 && K % 2 == 0, "split kernel needs an even K");
-  static constexpr int HN = NB / 2;       // window rows per lane half and reflector
-  static constexpr int NG = NB / 32;      // full 16-value segments per lane half
-  static constexpr int HS = HN + 2;       // packed half: HN+1 values, then tau / zero
-  static constexpr int RS = 2 * HS;       // packed reflector record
-  static constexpr int R = (NB + K) / 2;  // registers per lane (W + 1 rows)
-  static constexpr int64_t SW = 32;       // columns per stripe
-};
-
-// Packed record of reflector (s0+o, j), o = 0..K-1, written by one block.
-template <typename E, int NB, int K>
-__device__ __forceinline__ void pack_group(const E* __restrict__ hh, const E* __restrict__ tau,
-                                           int64_t n, int64_t m, int64_t j, int64_t Jmax,
-                                           E* __restrict__ P) {
-  using Gm = SplitGeom<NB, K>;
-  const int64_t s0 = m * K;
-  const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
-  if (j >= J0) return;  // never read
-  const int64_t ctot = csum(n - 1, NB);
-  E* __restrict__ rec = P + ((m * Jmax + j) * K) * Gm::RS;
-  for (int e = (int)threadIdx.x; e < K * Gm::RS; e += (int)blockDim.x) {
-    const int o = e / Gm::RS, rem = e - o * Gm::RS;
-    const int h = rem / Gm::HS, t = rem - h * Gm::HS;
-    const int64_t s = s0 + o;
-    const bool valid = (s <= n - 2) && (j < (n - 1 - s + NB - 1) / NB);
-    E v{};
-    if (valid) {
-      const int64_t slot = ctot - csum(n - 1 - s, NB) + j;
-      if (h == 0 && t == Gm::HS - 1) {
-        v = tau[slot];
-      } else {
-        const int64_t r = s + 1 + j * NB;
-        const int64_t L = (NB < n - r) ? NB : n - r;
-        const int i = 2 * t + h - (o & 1);
-        if (i >= 0 && i < L) v = hh[slot * NB + i];
-      }
-    }
-    // real records: the second half's spare slot of an even offset holds the
-    // pair coupling, written below
-    if (std::is_floating_point<E>::value && h == 1 && t == Gm::HS - 1 && (o & 1) == 0) continue;
-    rec[e] = v;
-  }
-  if constexpr (std::is_floating_point<E>::value) {
-    // pair coupling c = vB.vA of B = offset o (even) and A = o+1 (vA starts one
-    // window row below vB): one wave per pair, a fixed-order tree sum in fp64
-    const int wave = (int)threadIdx.x >> 6, lane = (int)threadIdx.x & 63;
-    for (int o = 2 * wave; o < K; o += 2 * ((int)blockDim.x >> 6)) {
-      const int64_t s = s0 + o, sa = s + 1;
-      const bool vb = (s <= n - 2) && (j < (n - 1 - s + NB - 1) / NB);
-      const bool va = o + 1 < K && (sa <= n - 2) && (j < (n - 1 - sa + NB - 1) / NB);
-      double prod = 0.0;
-      if (vb && va) {
-        const int64_t rb = s + 1 + j * NB;
-        const int64_t lb = (NB < n - rb) ? NB : n - rb;
-        const int64_t la = (NB < n - rb - 1) ? NB : n - rb - 1;
-        if (lane + 1 < lb && lane < la) {
-          const int64_t slot_b = ctot - csum(n - 1 - s, NB) + j;
-          const int64_t slot_a = ctot - csum(n - 1 - sa, NB) + j;
-          prod = (double)hh[slot_b * NB + lane + 1] * (double)hh[slot_a * NB + lane];
-        }
-      }
-#pragma unroll
-      for (int w = 32; w >= 1; w >>= 1) prod += __shfl_xor(prod, w, 64);
-      if (lane == 0) rec[o * Gm::RS + Gm::RS - 1] = (E)prod;
-    }
-  }
-}
-
-template <typename E, int NB, int K>
-__global__ __launch_bounds__(256) void k_pack_split(const E* __restrict__ hh,
-                                                    const E* __restrict__ tau, int64_t n,
-                                                    int64_t Jmax, E* __restrict__ P) {
-  const int64_t g = blockIdx.x;
-  pack_group<E, NB, K>(hh, tau, n, g / Jmax, g % Jmax, Jmax, P);
-}
-
-template <typename E, int NB, int K>
-__global__ __launch_bounds__(256) void k_pack_split_b(const ProblemDesc* __restrict__ d,
-                                                      int count) {
-  const int b = (int)blockIdx.x;
-  const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::ptile0>(d, count, b)];
-  const int64_t g = b - D.ptile0;
-  pack_group<E, NB, K>((const E*)D.hh, (const E*)D.tau, D.n, g / D.Jmax, g % D.Jmax, D.Jmax,
-                       (E*)D.P);
-}
-
-// Layout conversion between Q (column major) and SW-column stripes, element
-// (r, SW*c + l) at Qs[(c*rows_pad + r)*SW + l]; 64 x 64 tiles through LDS,
-// padding rows and columns written as zeros.
-template <typename E, int SW>
-__device__ __forceinline__ void to_rows_tile_sw(const E* __restrict__ Q, int64_t ldq,
-                                                int64_t n, int64_t nev, E* __restrict__ Qs,
-                                                int64_t rows_pad, int64_t G, int64_t rt,
-                                                int64_t ct, E (*tile)[65]) {
-  const int64_t r0 = rt * 64, c0 = ct * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t r = r0 + tx, col = c0 + cc;
-    tile[cc][tx] = (r < n && col < nev) ? Q[r + col * ldq] : E{};
-  }
-  __syncthreads();
-  const int64_t col = c0 + tx, c = col / SW, l = col - c * SW;
-  if (c >= G) return;
-  E* __restrict__ dst = Qs + c * rows_pad * SW + l;
-  for (int rr = ty; rr < 64; rr += 4) {
-    const int64_t r = r0 + rr;
-    if (r < rows_pad) dst[r * SW] = tile[tx][rr];
-  }
-}
-
-template <typename E, int SW>
-__device__ __forceinline__ void from_rows_tile_sw(const E* __restrict__ Qs, int64_t rows_pad,
-                                                  E* __restrict__ Q, int64_t ldq, int64_t n,
-                                                  int64_t nev, int64_t G, int64_t rt, int64_t ct,
-                                                  E (*tile)[65]) {
-  const int64_t r0 = rt * 64, c0 = ct * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  {
-    const int64_t col = c0 + tx, c = col / SW, l = col - c * SW;
-    for (int rr = ty; rr < 64; rr += 4) {
-      const int64_t r = r0 + rr;
-      if (r < n && c < G) tile[rr][tx] = Qs[(c * rows_pad + r) * SW + l];
-    }
-  }
-  __syncthreads();
-  for (int cc = ty; cc < 64; cc += 4) {
-    const int64_t r = r0 + tx, col = c0 + cc;
-    if (r < n && col < nev) Q[r + col * ldq] = tile[tx][cc];
-  }
-}
-
-template <typename E, int SW>
-__global__ __launch_bounds__(256) void k_to_rows_sw(const E* __restrict__ Q, int64_t ldq,
-                                                    int64_t n, int64_t nev,
-                                                    E* __restrict__ Qs, int64_t rows_pad,
-                                                    int64_t G) {
-  __shared__ E tile[64][65];
-  to_rows_tile_sw<E, SW>(Q, ldq, n, nev, Qs, rows_pad, G, blockIdx.x, blockIdx.y, tile);
-}
-
-template <typename E, int SW>
-__global__ __launch_bounds__(256) void k_from_rows_sw(const E* __restrict__ Qs,
-                                                      int64_t rows_pad, E* __restrict__ Q,
-                                                      int64_t ldq, int64_t n, int64_t nev,
-                                                      int64_t G) {
-  __shared__ E tile[64][65];
-  from_rows_tile_sw<E, SW>(Qs, rows_pad, Q, ldq, n, nev, G, blockIdx.x, blockIdx.y, tile);
-}
-
-template <typename E, int SW>
-__global__ __launch_bounds__(256) void k_to_rows_sw_b(const ProblemDesc* __restrict__ d,
-                                                      int count) {
-  __shared__ E tile[64][65];
-  const int t = (int)blockIdx.x;
-  const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::tile0>(d, count, t)];
-  const int local = t - D.tile0;
-  to_rows_tile_sw<E, SW>((const E*)D.Q, D.ldq, D.n, D.nev, (E*)D.Qs, D.rows_pad, D.G,
-                      local / D.GT, local % D.GT, tile);
-}
-
-template <typename E, int SW>
-__global__ __launch_bounds__(256) void k_from_rows_sw_b(const ProblemDesc* __restrict__ d,
-                                                        int count) {
-  __shared__ E tile[64][65];
-  const int t = (int)blockIdx.x;
-  const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::otile0>(d, count, t)];
-  const int local = t - D.otile0;
-  from_rows_tile_sw<E, SW>((const E*)D.Qs, D.rows_pad, (E*)D.Q, D.ldq, D.n, D.nev, D.G,
-                        local / D.GT, local % D.GT, tile);
-}
-
-// Sum of a value over the two lane halves (lanes l and l^32), computed in the
-// same order in both halves so that they agree bitwise.
-__device__ __forceinline__ double half_pair_sum(double s) {
-  const unsigned lo = (unsigned)__double2loint(s), hi = (unsigned)__double2hiint(s);
-  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
-  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
-  // element 0: lower half's value in every lane; element 1: upper half's
-  return __hiloint2double((int)rh[0], (int)rl[0]) + __hiloint2double((int)rh[1], (int)rl[1]);
-}
-
-__device__ __forceinline__ float half_pair_sum(float s) {
-  const unsigned u = __float_as_uint(s);
-  const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
-  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-}
-
-__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-
-// Reflector pairs (A = odd offset o, applied first; B = o-1): the two dot
-// products wA = vA.x and wB = vB.x are taken together on the window as it is
-// before A, and B's is corrected for A's update with the pair coupling
-// c = vB.vA, stored by the packing pass in B's record:
-//   nwA = -tauA wA,  nwB = -tauB (wB + c nwA),  x += vA nwA + vB nwB,
-// which is (I - tauB vB vB^T)(I - tauA vA vA^T) x.  Both reflectors start on
-// register o/2 of each lane half; one reduction across the halves serves the
-// pair.
-template <typename T>
-struct SplitPair {
-  T a0, a1, a2, ta, b0, b1, tb, c;
-};
-
-template <int NB, int K, int o, typename T>
-__device__ __forceinline__ SplitPair<T> split_load_pair(const T* __restrict__ Pj, int voff,
-                                                        int z) {
-  using Gm = SplitGeom<NB, K>;
-  static_assert((o & 1) == 1, "A is the odd offset of a pair");
-  const T* __restrict__ ra = Pj + o * Gm::RS + z;
-  const T* __restrict__ rb = ra - Gm::RS;
-  SplitPair<T> s;
-  s.a0 = ra[voff];
-  s.a1 = (Gm::NG == 2) ? ra[voff + 16] : T(0);
-  s.a2 = ra[voff + 16 * Gm::NG];
-  s.ta = ra[Gm::HS - 1];
-  s.b0 = rb[voff];
-  s.b1 = (Gm::NG == 2) ? rb[voff + 16] : T(0);
-  s.tb = rb[Gm::HS - 1];
-  s.c = rb[Gm::RS - 1];
-  return s;
-}
-
-// T = double or float (the same blocks on 64- or 32-bit values)
-template <int NB, int K, int PD, typename T, int R>
-__device__ __forceinline__ void step_split_pair(T (&x)[R], const T* __restrict__ Pj, int voff) {
-  using Gm = SplitGeom<NB, K>;
-  constexpr int NP = K / 2, HN = Gm::HN, NG = Gm::NG;
-  static_assert(R == Gm::R, "window register count");
-  static_assert(PD >= 1 && PD <= 3 && PD < NP, "pair prefetch distance 1..3");
-  SplitPair<T> buf[PD];
-  FwdFor<PD>::run([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    buf[i] = split_load_pair<NB, K, K - 1 - 2 * i>(Pj, voff, 0);
-  });
-  RevFor<NP>::run([&](auto pc) {
-    constexpr int pi = decltype(pc)::value;
-    constexpr int p0 = pi;  // (2 pi + 1) >> 1
-    const SplitPair<T> c0 = buf[0];
-    T aA0 = T(0), aA1 = T(0), aB0 = T(0), aB1 = T(0);
-    if constexpr (NG == 2)
-      pdot2_a(aA0, aA1, aB0, aB1, c0.a0, c0.a1, c0.b0, c0.b1, &x[p0], &x[p0 + 16]);
-    else
-      pdot1_a(aA0, aA1, aB0, aB1, c0.a0, c0.b0, &x[p0]);
-    SplitPair<T> nn{};
-    if constexpr (pi - PD >= 0)
-      nn = split_load_pair<NB, K, 2 * (pi - PD) + 1>(Pj, voff, zero_after(aA0));
-    if constexpr (NG == 2)
-      pdot2_b(aA0, aA1, aB0, aB1, c0.a0, c0.a1, c0.b0, c0.b1, c0.a2, &x[p0 + 8], &x[p0 + 24],
-              &x[p0 + HN]);
-    else
-      pdot1_b(aA0, aA1, aB0, aB1, c0.a0, c0.b0, c0.a2, &x[p0 + 8], &x[p0 + HN]);
-    const T wA = half_pair_sum(aA0 + aA1);
-    const T wB = half_pair_sum(aB0 + aB1);
-    const T nwA = -(c0.ta * wA);
-    const T nwB = -(c0.tb * fma_t(c0.c, nwA, wB));
-    if constexpr (NG == 2) {
-      pupd2_a(&x[p0], &x[p0 + 16], c0.a0, c0.a1, c0.b0, c0.b1, nwA, nwB);
-      pupd2_b(&x[p0 + 8], &x[p0 + 24], &x[p0 + HN], c0.a0, c0.a1, c0.b0, c0.b1, c0.a2, nwA, nwB);
-    } else {
-      pupd1_a(&x[p0], c0.a0, c0.b0, nwA, nwB);
-      pupd1_b(&x[p0 + 8], &x[p0 + HN], c0.a0, c0.b0, c0.a2, nwA, nwB);
-    }
-    FwdFor<PD - 1>::run([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      buf[i] = buf[i + 1];
-    });
-    buf[PD - 1] = nn;
-  });
-}
-
-// Complex counterpart: record values are complex (re, im), reflector o's
-// dot product conj(v)^T x and update x += v nw with nw = -tau (dot), each
-// complex product as four fp64 FMAs with a broadcast reflector operand.
-struct SplitValsC {
-  z64 v0, v1, v2, t;
-};
-
-template <int NB, int K, int o>
-__device__ __forceinline__ SplitValsC split_load_c(const z64* __restrict__ Pj, int voff, int z) {
-  using Gm = SplitGeom<NB, K>;
-  const z64* __restrict__ rec = Pj + o * Gm::RS + z;
-  SplitValsC s;
-  s.v0 = rec[voff];
-  s.v1 = (Gm::NG == 2) ? rec[voff + 16] : z64{0.0, 0.0};
-  s.v2 = (o & 1) ? rec[voff + 16 * Gm::NG] : z64{0.0, 0.0};
-  s.t = rec[Gm::HS - 1];
-  return s;
-}
-
-template <int NB, int K, int PD, int R>
-__device__ __forceinline__ void step_split_c(z64 (&x)[R], const z64* __restrict__ Pj, int voff) {
-  using Gm = SplitGeom<NB, K>;
-  static_assert(R == Gm::R, "window register count");
-  static_assert(PD >= 1 && PD <= 4 && PD < K, "prefetch distance 1..4");
-  constexpr int HN = Gm::HN, NG = Gm::NG;
-  SplitValsC buf[PD];
-  FwdFor<PD>::run([&](auto ic) {
-    constexpr int i = decltype(ic)::value;
-    buf[i] = split_load_c<NB, K, K - 1 - i>(Pj, voff, 0);
-  });
-  RevFor<K>::run([&](auto oc) {
-    constexpr int o = decltype(oc)::value;
-    constexpr int p0 = o >> 1;
-    const SplitValsC c0 = buf[0];
-    double a0r = 0.0, a0i = 0.0, a1r = 0.0, a1i = 0.0;
-    if constexpr (NG == 2) {
-      cdot_a(a0r, a0i, c0.v0.re, c0.v0.im, &x[p0]);
-      cdot_a(a1r, a1i, c0.v1.re, c0.v1.im, &x[p0 + 16]);
-    } else {
-      cdot_a(a0r, a0i, c0.v0.re, c0.v0.im, &x[p0]);
-    }
-    SplitValsC nn{};
-    if constexpr (o - PD >= 0) nn = split_load_c<NB, K, o - PD>(Pj, voff, zero_after(a0r));
-    if constexpr (NG == 2) {
-      cdot_b(a0r, a0i, c0.v0.re, c0.v0.im, &x[p0 + 8]);
-      cdot_b(a1r, a1i, c0.v1.re, c0.v1.im, &x[p0 + 24]);
-    } else {
-      cdot_b(a1r, a1i, c0.v0.re, c0.v0.im, &x[p0 + 8]);
-    }
-    if constexpr ((o & 1) != 0) cdot_x(a0r, a0i, c0.v2.re, c0.v2.im, x[p0 + HN]);
-    const double tr = half_pair_sum(a0r + a1r), ti = half_pair_sum(a0i + a1i);
-    const double nr = -(c0.t.re * tr - c0.t.im * ti), ni = -(c0.t.re * ti + c0.t.im * tr);
-    if constexpr (NG == 2) {
-      cupd_a(&x[p0], c0.v0.re, c0.v0.im, nr, ni);
-      cupd_a(&x[p0 + 16], c0.v1.re, c0.v1.im, nr, ni);
-      cupd_b(&x[p0 + 8], c0.v0.re, c0.v0.im, nr, ni);
-      cupd_b(&x[p0 + 24], c0.v1.re, c0.v1.im, nr, ni);
-    } else {
-      cupd_a(&x[p0], c0.v0.re, c0.v0.im, nr, ni);
-      cupd_b(&x[p0 + 8], c0.v0.re, c0.v0.im, nr, ni);
-    }
-    if constexpr ((o & 1) != 0) cupd_x(x[p0 + HN], c0.v2.re, c0.v2.im, nr, ni);
-    FwdFor<PD - 1>::run([&](auto ic) {
-      constexpr int i = decltype(ic)::value;
-      buf[i] = buf[i + 1];
-    });
-    buf[PD - 1] = nn;
-  });
-}
-
-// One tile: group q (chase steps [qS, min(qS+S, J0))) of block m on stripe c.
-// Row pair (row0+2p, row0+2p+1) of the stripe is the 64 values at
-// Qs + (c*rows_pad + row0)*32 + 64p, lane l taking element l.
-template <typename E, int NB, int K, int PD>
-__device__ __forceinline__ void run_split_tile(const E* __restrict__ P, int64_t Jmax,
-                                               E* __restrict__ Qs, int64_t rows_pad,
-                                               int64_t n, int64_t c, int64_t m, int64_t q,
-                                               int64_t S) {
-  using Gm = SplitGeom<NB, K>;
-  constexpr int R = Gm::R, HN = Gm::HN;
-  const int lane = threadIdx.x;
-  const int voff = (lane >> 5) * Gm::HS + (lane & 15);
-  E* __restrict__ bp = Qs + c * rows_pad * Gm::SW;
-  const int64_t s0 = m * K;
-  const int64_t J0 = (n - 1 - s0 + NB - 1) / NB;
-  const int64_t j0 = q * S;
-  const int64_t j1 = (j0 + S < J0) ? j0 + S : J0;
-  E x[R];
-  for (int64_t j = j0; j < j1; ++j) {
-    E* __restrict__ rp = bp + (s0 + 1 + j * NB) * Gm::SW;  // uniform
-    if (j == j0) {
-#pragma unroll
-      for (int p = 0; p < R; ++p) x[p] = rp[p * 64 + lane];
-    } else {
-#pragma unroll
-      for (int p = 0; p < R - HN; ++p) x[p] = x[p + HN];
-#pragma unroll
-      for (int p = R - HN; p < R; ++p) x[p] = rp[p * 64 + lane];
-    }
-    if constexpr (std::is_same<E, double>::value || std::is_same<E, float>::value)
-      step_split_pair<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
-    else
-      step_split_c<NB, K, PD>(x, P + ((m * Jmax + j) * K) * Gm::RS, voff);
-#pragma unroll
-    for (int p = 0; p < HN; ++p) rp[p * 64 + lane] = x[p];
-  }
-  // window rows NB .. W-1 carried to the next group (or final); the extra row
-  // W (upper half of the last register) is not written
-  E* __restrict__ rl = bp + (s0 + 1 + (j1 - 1) * NB) * Gm::SW;
-#pragma unroll
-  for (int p = HN; p < R - 1; ++p) rl[p * 64 + lane] = x[p];
-  if (lane < 32) rl[(R - 1) * 64 + lane] = x[R - 1];
-}
-
-// Stripes c0 .. c0+G-1 of the launch's blocks m0 .. m0+gridDim.x/G-1.
-template <typename E, int NB, int K, int OCC, int PD>
-__global__ __launch_bounds__(64, OCC) void k_split(const E* __restrict__ P, int64_t Jmax,
-                                                   E* __restrict__ Qs, int64_t rows_pad,
-                                                   int64_t n, int c0, int G, int M, int t, int m0,
-                                                   int S, int xcd) {
-  const int b = tile_of((int)blockIdx.x, (int)gridDim.x, xcd);
-  const int c = c0 + b % G;
-  const int m = m0 + b / G;
-  run_split_tile<E, NB, K, PD>(P, Jmax, Qs, rows_pad, n, c, m, t - (M - 1 - m), S);
-}
-
-template <typename E, int NB, int K, int OCC, int PD>
-__global__ __launch_bounds__(64, OCC) void k_split_b(const ProblemDesc* __restrict__ d,
-                                                     const DiagEntry* __restrict__ e, int ecount,
-                                                     int t, int xcd) {
-  const int b = tile_of((int)blockIdx.x, (int)gridDim.x, xcd);
-  const DiagEntry& E0 = e[find_by<DiagEntry, &DiagEntry::tile0>(e, ecount, b)];
-  const ProblemDesc& D = d[E0.p];
-  const int local = b - E0.tile0;
-  const int m = E0.m0 + local / D.G;
-  run_split_tile<E, NB, K, PD>((const E*)D.P, D.Jmax, (E*)D.Qs, D.rows_pad, D.n, local % D.G,
-                        m, t - (D.M - 1 - m), D.S);
-}
-
-// ---------------------------------------------------------------------------
-// launchers
-// ---------------------------------------------------------------------------
-template <typename E, int NB, int K>
-size_t split_pbytes(int64_t M, int64_t Jmax) {
-  // + 32 values: the extra-segment loads of the last record read past it
-  return align256(((size_t)M * (size_t)Jmax * K * SplitGeom<NB, K>::RS + 32) * sizeof(E));
-}
-
-template <typename E, int NB, int K, int OCC, int PD>
-hipError_t launch_split(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
-                        int64_t nev, TileOpts opt, hipStream_t st, int num_cu) {
-  using Gm = SplitGeom<NB, K>;
-  static const int64_t slots = wave_slots(k_split<E, NB, K, OCC, PD>, num_cu);
-  const int64_t S = opt.steps > 0 ? opt.steps : choose_steps(n, nev, NB, K, slots, Gm::SW);
-  const DiagPlan pl(n, nev, NB, K, S, Gm::SW);
-  const int64_t Jmax = (n - 1 + NB - 1) / NB;
-  if (pl.G * pl.M >= INT32_MAX || pl.M * Jmax >= INT32_MAX || n + NB + K >= INT32_MAX)
-    return hipErrorInvalidValue;
-  const size_t pbytes = split_pbytes<E, NB, K>(pl.M, Jmax);
-  char* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, pbytes + pl.template qbytes<E>(), st);
-  if (err != hipSuccess) return err;
-  E* Pk = (E*)ws;
-  E* Qs = (E*)(ws + pbytes);
-  const unsigned gt = (unsigned)((nev + 63) / 64);
-  hipLaunchKernelGGL((k_pack_split<E, NB, K>), dim3((unsigned)(pl.M * Jmax)), dim3(256), 0, st,
-                     (const E*)hh, (const E*)tau, n, Jmax, Pk);
-  hipLaunchKernelGGL((k_to_rows_sw<E, Gm::SW>), dim3((unsigned)(pl.rows_pad / 64), gt), dim3(256), 0,
-                     st, (const E*)Q, ldq, n, nev, Qs, pl.rows_pad, pl.G);
-  const int ns = (int)std::max<int64_t>(1, std::min<int64_t>(opt.streams, pl.G));
-  ProfScope prof(st, K, S, ns);
-  {
-    // stripe groups: one launch sequence each, on concurrent streams when
-    // more than one (columns are independent; a group's launch tails overlap
-    // the other groups' launches)
-    StreamFork fork(st, ns);
-    if (fork.error() != hipSuccess) {
-      (void)hipFreeAsync(ws, st);
-      return fork.error();
-    }
-    for (int64_t t = 0; t < pl.T; ++t) {
-      int64_t m0, cnt;
-      pl.active(t, &m0, &cnt);
-      if (cnt == 0) continue;
-      for (int i = 0; i < ns; ++i) {
-        const int64_t c_lo = pl.G * i / ns, gs = pl.G * (i + 1) / ns - c_lo;
-        prof.before(fork.stream(i));
-        hipLaunchKernelGGL((k_split<E, NB, K, OCC, PD>), dim3((unsigned)(cnt * gs)), dim3(64), 0,
-                           fork.stream(i), (const E*)Pk, Jmax, Qs, pl.rows_pad, n, (int)c_lo,
-                           (int)gs, (int)pl.M, (int)t, (int)m0, (int)S, opt.xcd);
-        prof.after(fork.stream(i));
-      }
-    }
-    err = fork.join();
-  }
-  prof.end();
-  if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
-    return err;
-  }
-  hipLaunchKernelGGL((k_from_rows_sw<E, Gm::SW>), dim3((unsigned)((n + 63) / 64), gt), dim3(256), 0,
-                     st, (const E*)Qs, pl.rows_pad, (E*)Q, ldq, n, nev, pl.G);
-  err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(ws, st);
-  return err != hipSuccess ? err : e2;
-}
-
-// Batched: problems idx[0..cnt) of probs (real fp64, semi-bandwidth NB,
-// validated by the caller); all problems' diagonal schedules run side by side.
-template <typename E, int NB, int K, int OCC, int PD>
-hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
-                                TileOpts opt, hipStream_t st, int num_cu) {
-  using Gm = SplitGeom<NB, K>;
-  const int64_t S = opt.steps;
-  static const int64_t slots = wave_slots(k_split_b<E, NB, K, OCC, PD>, num_cu);
-  std::vector<ProblemDesc> d;
-  std::vector<DiagPlan> plans;
-  int64_t total_cols = 0;
-  for (int64_t i = 0; i < cnt; ++i) {
-    const elpa_hh_problem& p = probs[idx[i]];
-    if (p.n > 1 && p.nev > 0) total_cols += p.nev;
-  }
-  for (int64_t i = 0; i < cnt; ++i) {
-    const elpa_hh_problem& p = probs[idx[i]];
-    if (p.n <= 1 || p.nev == 0) continue;
-    const int64_t s = S > 0 ? S : choose_steps(p.n, total_cols, NB, K, slots, Gm::SW);
-    plans.emplace_back(p.n, p.nev, NB, K, s, Gm::SW);
-    ProblemDesc x{};
-    x.hh = p.hh;
-    x.tau = p.tau;
-    x.Q = p.Q;
-    x.n = p.n;
-    x.nev = p.nev;
-    x.ldq = p.ldq;
-    d.push_back(x);
-  }
-  if (d.empty()) return hipSuccess;
-  size_t off = 0, tiles = 0, otiles = 0, ptiles = 0;
-  int64_t T = 0;
-  std::vector<size_t> pat(d.size()), qat(d.size());
-  for (size_t i = 0; i < d.size(); ++i) {
-    const DiagPlan& pl = plans[i];
-    const int64_t Jmax = (pl.n - 1 + NB - 1) / NB;
-    d[i].G = (int)pl.G;
-    d[i].GT = (int)((pl.nev + 63) / 64);
-    d[i].M = (int)pl.M;
-    d[i].S = (int)pl.S;
-    d[i].rows_pad = pl.rows_pad;
-    d[i].Jmax = Jmax;
-    d[i].tile0 = (int)tiles;
-    d[i].otile0 = (int)otiles;
-    d[i].ptile0 = (int)ptiles;
-    tiles += (size_t)(pl.rows_pad / 64 * d[i].GT);
-    otiles += (size_t)((pl.n + 63) / 64 * d[i].GT);
-    ptiles += (size_t)(pl.M * Jmax);
-    pat[i] = off;
-    off += split_pbytes<E, NB, K>(pl.M, Jmax);
-    qat[i] = off;
-    off += pl.template qbytes<E>();
-    T = std::max(T, pl.T);
-  }
-  std::vector<DiagEntry> ent;
-  std::vector<int64_t> eoff((size_t)T + 1, 0), etiles((size_t)T, 0);
-  for (int64_t t = 0; t < T; ++t) {
-    eoff[(size_t)t] = (int64_t)ent.size();
-    int64_t tl = 0;
-    for (size_t i = 0; i < d.size(); ++i) {
-      int64_t m0, c;
-      plans[i].active(t, &m0, &c);
-      if (c == 0) continue;
-      ent.push_back(DiagEntry{(int)i, (int)m0, (int)c, (int)tl});
-      tl += c * plans[i].G;
-    }
-    etiles[(size_t)t] = tl;
-  }
-  eoff[(size_t)T] = (int64_t)ent.size();
-  if (tiles >= (size_t)INT32_MAX || otiles >= (size_t)INT32_MAX || ptiles >= (size_t)INT32_MAX)
-    return hipErrorInvalidValue;
-  for (int64_t x : etiles)
-    if (x >= INT32_MAX) return hipErrorInvalidValue;
-  const size_t dbytes = align256(d.size() * sizeof(ProblemDesc));
-  const size_t ebytes = align256(std::max<size_t>(1, ent.size()) * sizeof(DiagEntry));
-  char* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, dbytes + ebytes + off, st);
-  if (err != hipSuccess) return err;
-  for (size_t i = 0; i < d.size(); ++i) {
-    d[i].P = ws + dbytes + ebytes + pat[i];
-    d[i].Qs = ws + dbytes + ebytes + qat[i];
-  }
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  PinnedStaging& stage = PinnedStaging::for_device(dev);
-  err = stage.upload(ws, d.data(), d.size() * sizeof(ProblemDesc), st);
-  if (err == hipSuccess && !ent.empty())
-    err = stage.upload(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry), st);
-  if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
-    return err;
-  }
-  const ProblemDesc* dd = (const ProblemDesc*)ws;
-  const DiagEntry* de = (const DiagEntry*)(ws + dbytes);
-  const int count = (int)d.size();
-  hipLaunchKernelGGL((k_pack_split_b<E, NB, K>), dim3((unsigned)ptiles), dim3(256), 0, st, dd, count);
-  hipLaunchKernelGGL((k_to_rows_sw_b<E, Gm::SW>), dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
-  ProfScope prof(st, K, S);
-  for (int64_t t = 0; t < T; ++t) {
-    const int64_t ne = eoff[(size_t)t + 1] - eoff[(size_t)t];
-    if (ne == 0) continue;
-    prof.before(st);
-    hipLaunchKernelGGL((k_split_b<E, NB, K, OCC, PD>), dim3((unsigned)etiles[(size_t)t]), dim3(64), 0,
-                       st, dd, de + eoff[(size_t)t], (int)ne, (int)t, opt.xcd);
-    prof.after(st);
-  }
-  prof.end();
-  hipLaunchKernelGGL((k_from_rows_sw_b<E, Gm::SW>), dim3((unsigned)otiles), dim3(256), 0, st, dd,
-                     count);
-  err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(ws, st);
-  return err != hipSuccess ? err : e2;
-}
-
-template <typename E, int NB, int K>
-size_t split_workspace(int64_t n, int64_t nev) {
-  const DiagPlan pl(n, nev, NB, K, 1, SplitGeom<NB, K>::SW);
-  return split_pbytes<E, NB, K>(pl.M, (n - 1 + NB - 1) / NB) + pl.template qbytes<E>();
-}
-
-#define EHH_SPLIT(E, DT, NB, K, OCC, PD)                                               \
-  {ELPA_PATH_SPLIT, DT, NB, K, OCC, &launch_split<E, NB, K, OCC, PD>,              \
-   &launch_split_batched<E, NB, K, OCC, PD>, &split_workspace<E, NB, K>}
+const StripeEntry* split_table_r64(int* size);
+const StripeEntry* split_table_r32(int* size);
+const StripeEntry* split_table_c64(int* size);
 
 const StripeEntry* split_table(int* size) {
-  static const StripeEntry table[] = {
-      EHH_SPLIT(double, 0, 32, 32, 2, 1), EHH_SPLIT(double, 0, 32, 64, 2, 1),
-      EHH_SPLIT(double, 0, 32, 96, 2, 1),
-      // real: reflector pairs, the last number the pairs whose values are in
-      // flight; k = 48 and 64 fit three waves per SIMD, k = 80 two
-      EHH_SPLIT(double, 0, 64, 48, 2, 1), EHH_SPLIT(double, 0, 64, 64, 2, 1),
-      EHH_SPLIT(double, 0, 64, 80, 2, 2),
-      // fp32: one register per value, up to four waves per SIMD
-      EHH_SPLIT(float, 1, 64, 64, 4, 2), EHH_SPLIT(float, 1, 64, 80, 4, 2),
-      EHH_SPLIT(float, 1, 64, 96, 4, 1),
-      EHH_SPLIT(float, 1, 32, 64, 4, 2), EHH_SPLIT(float, 1, 32, 96, 4, 2),
-      EHH_SPLIT(float, 1, 32, 128, 3, 1),
-      // complex: each window register holds two fp64 values
-      EHH_SPLIT(z64, 2, 64, 16, 2, 2), EHH_SPLIT(z64, 2, 64, 24, 2, 1),
-      EHH_SPLIT(z64, 2, 32, 32, 2, 2), EHH_SPLIT(z64, 2, 32, 48, 2, 1),
-  };
-  *size = (int)(sizeof(table) / sizeof(table[0]));
-  return table;
+  static const std::vector<StripeEntry> all = [] {
+    std::vector<StripeEntry> v;
+    for (auto part : {split_table_r64, split_table_r32, split_table_c64}) {
+      int c = 0;
+      const StripeEntry* t = part(&c);
+      v.insert(v.end(), t, t + c);
+    }
+    return v;
+  }();
+  *size = (int)all.size();
+  return all.data();
 }
 
 }  // namespace ehh

@@ -1,0 +1,20 @@
+// One-lane stripe kernel instances for real fp32 (one translation unit per
+// element type, so that the kernel variants compile in parallel).
+#include "hh_kernels_impl.h"
+
+namespace ehh {
+
+#define EHH_DIAG(E, DT, NB, K, OCC)                                                    \
+  {ELPA_PATH_STRIPE, DT, NB, K, OCC, &launch_diag<E, NB, K, OCC>,                        \
+   &launch_diag_batched<E, NB, K, OCC>, &diag_workspace<E, NB, K>}
+
+const StripeEntry* stripe_table_r32(int* size) {
+  static const StripeEntry table[] = {
+      EHH_DIAG(float, 1, 32, 16, 2),  EHH_DIAG(float, 1, 32, 32, 2),
+      EHH_DIAG(float, 1, 64, 16, 2),  EHH_DIAG(float, 1, 64, 32, 1),
+  };
+  *size = (int)(sizeof(table) / sizeof(table[0]));
+  return table;
+}
+
+}  // namespace ehh

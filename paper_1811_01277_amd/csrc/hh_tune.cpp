@@ -50,7 +50,7 @@ Key key_of(int32_t dtype, int64_t nbw, int64_t n, int64_t nev) {
 bool plan_valid(const elpa_hh_plan& p) {
   return p.path >= ELPA_PATH_AUTO && p.path <= ELPA_PATH_WY && p.k >= 0 && p.steps >= 0 &&
          p.order >= ELPA_ORDER_AUTO && p.order <= ELPA_ORDER_XCD && p.streams >= 0 &&
-         p.streams <= 8 && p.reserved == 0;
+         p.streams <= 8 && p.batch >= ELPA_BATCH_AUTO && p.batch <= ELPA_BATCH_DIAGONAL;
 }
 
 }  // namespace
@@ -255,12 +255,24 @@ int elpa_hh_tune_batched(const elpa_hh_problem* probs, int64_t count, void* stre
                                                            : ehh::stripe_table(&cnt);
       for (int i = 0; i < cnt; ++i) ks.insert(tab[i].k);
     }
-    for (int k : ks)
+    for (int k : ks) {
+      if (fam == ELPA_PATH_SPLIT) {
+        // the two-lane family's batched schedules: one launch, or the
+        // diagonal sequence at each tile height (one stream either way)
+        const elpa_hh_plan one{fam, k, 0, 0, 1, ELPA_BATCH_ONE_LAUNCH};
+        if (elpa_hh_workspace_bytes_batched(probs, count, &one) >= 0) cand.push_back(one);
+        for (int si = 0; si < nsteps; ++si) {
+          const elpa_hh_plan p{fam, k, steps_list[si], 0, 1, ELPA_BATCH_DIAGONAL};
+          if (elpa_hh_workspace_bytes_batched(probs, count, &p) >= 0) cand.push_back(p);
+        }
+        continue;
+      }
       for (int si = 0; si < nsteps; ++si)
         for (int streams : {1, 2}) {
           const elpa_hh_plan p{fam, k, steps_list[si], 0, streams, 0};
           if (elpa_hh_workspace_bytes_batched(probs, count, &p) >= 0) cand.push_back(p);
         }
+    }
   }
   if (cand.empty()) cand.push_back(elpa_hh_plan{ELPA_PATH_REF, 0, 0, 0, 0, 0});
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -402,7 +414,7 @@ elpa_hh_autotune_state* elpa_hh_autotune_setup(int32_t level, int64_t n, int64_t
   if (n <= 1 || nev <= 0 || nbw < 1) return nullptr;
   if (dtype != ELPA_R64 && dtype != ELPA_R32 && dtype != ELPA_C64) return nullptr;
   if (fixed && (fixed->k < 0 || fixed->steps < 0 || fixed->streams < 0 || fixed->streams > 8 ||
-                fixed->reserved != 0))
+                fixed->batch < ELPA_BATCH_AUTO || fixed->batch > ELPA_BATCH_DIAGONAL))
     return nullptr;
   auto* st = new elpa_hh_autotune_state();
   st->level = level;

@@ -437,7 +437,7 @@ hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int6
     return hipErrorInvalidValue;
   const size_t pbytes = wy_pbytes<E, NB, K>(pl.M, Jmax);
   char* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, pbytes + pl.template qbytes<E>(), st);
+  hipError_t err = ws_alloc((void**)&ws, pbytes + pl.template qbytes<E>(), st);
   if (err != hipSuccess) return err;
   E* Pk = (E*)ws;
   E* Qs = (E*)(ws + pbytes);
@@ -557,7 +557,7 @@ hipError_t launch_wy_batched(const elpa_hh_problem* probs, const int64_t* idx, i
   const size_t dbytes = align256(d.size() * sizeof(ProblemDesc));
   const size_t ebytes = align256(std::max<size_t>(1, ent.size()) * sizeof(DiagEntry));
   char* ws = nullptr;
-  hipError_t err = hipMallocAsync((void**)&ws, dbytes + ebytes + off, st);
+  hipError_t err = ws_alloc((void**)&ws, dbytes + ebytes + off, st);
   if (err != hipSuccess) return err;
   for (size_t i = 0; i < d.size(); ++i) {
     d[i].P = ws + dbytes + ebytes + pat[i];

@@ -136,8 +136,28 @@ def test_plan_support_table():
     assert rc == -6
     rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 0, 9)  # > 8 streams
     assert rc == -6
-    pl = P.binding._Plan(0, 0, 0, 0, 0, 1)                                  # reserved != 0
+    pl = P.binding._Plan(0, 0, 0, 0, 0, 3)                                  # unknown batch
     assert P.library().elpa_hh_trafo_plan(10, 5, 2, 8, 8, 8, 10, P.R64, None, C.byref(pl)) == -6
+
+
+def split_ws_brute(n, nev, nbw, k, es):
+    """Workspace of the two-lane kernel by direct summation: the stripe copy
+    of Q and the packed step records of every sweep block's existing steps."""
+    al = lambda x: -(-x // 256) * 256
+    rows_pad = -(-(n + nbw + k) // 64) * 64
+    M = -(-(n - 1) // k)
+    steps = sum(-(-(n - 1 - m * k) // nbw) for m in range(M))
+    rs = 2 * (nbw // 2 + 2)
+    return al((steps * k * rs + 32) * es) + al(M * 8) + al(rows_pad * (-(-nev // 32)) * 32 * es)
+
+
+@pytest.mark.parametrize("nbw,k", [(64, 48), (64, 64), (64, 80), (32, 32), (32, 64), (32, 96)])
+def test_split_workspace_matches_direct_sum(nbw, k):
+    # the library sums the blocks' step counts in closed form (a floor sum);
+    # every n from 2 to 400 plus a spread of large ones against the direct sum
+    for n in list(range(2, 401)) + [1000, 4097, 8192, 12345, 20000, 65537]:
+        assert P.workspace_bytes(n, 33, nbw, P.R64, P.PATH_SPLIT, k) == \
+            split_ws_brute(n, 33, nbw, k, 8), n
 
 
 def test_workspace_bytes():
@@ -148,12 +168,11 @@ def test_workspace_bytes():
     assert P.workspace_bytes(100, 10, 64, 9) == -1
     assert P.workspace_bytes(100, 10, 64, P.R64, P.PATH_SPLIT, 63) == -1
     # split path at n = nev = 20000, k = 80: stripe copy (rows_pad x 625 x 32 fp64)
-    # plus packed reflectors (M x Jmax x k records of 68 values, +32 values)
+    # plus packed reflectors: one record set of k records of 68 values per
+    # (sweep block m, existing chase step j < J0(m)), +32 values, and the
+    # table of each block's first record (M int64)
     n, nev, nbw, k = 20000, 20000, 64, 80
-    rows_pad = -(-(n + nbw + k) // 64) * 64
-    M, Jmax = -(-(n - 1) // k), -(-(n - 1) // nbw)
-    al = lambda x: -(-x // 256) * 256
-    want = al((M * Jmax * k * 68 + 32) * 8) + al(rows_pad * (-(-nev // 32)) * 32 * 8)
+    want = split_ws_brute(n, nev, nbw, k, 8)
     assert P.workspace_bytes(n, nev, nbw, P.R64, P.PATH_SPLIT, k) == want
     assert P.workspace_bytes(n, nev, nbw, P.R64) == want        # the library default
     assert P.workspace_bytes(n, nev, nbw, P.C64) > 0

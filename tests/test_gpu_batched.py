@@ -2,7 +2,9 @@
 
 * every problem of a batch matches the oracle (same bar as single calls);
 * a problem gives the bitwise same result alone and inside a batch (same
-  kernel variant, same per-task arithmetic);
+  kernel variant, same per-column arithmetic);
+* the problems of a batch that run the two-lane kernel run in one launch
+  (the batched workload included);
 * mixed element types and nbw in one call; an invalid problem rejects the
   whole call before anything runs.
 """
@@ -48,9 +50,11 @@ def rounded(x, dt):
     return x.astype(np.float32).astype(np.float64) if dt == "r32" else x
 
 
-def test_batch_matches_oracle_and_single_calls(torch_dev):
+@pytest.mark.parametrize("sched", ["one_launch", "diagonal", "auto"])
+def test_batch_matches_oracle_and_single_calls(torch_dev, sched):
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
+    batch = {"one_launch": P.BATCH_ONE_LAUNCH, "diagonal": P.BATCH_DIAGONAL, "auto": 0}[sched]
     sizes = [(65, 32, 65), (200, 32, 200), (333, 32, 101), (97, 32, 97), (512, 32, 512),
              (130, 64, 129), (260, 64, 64)]
     probs, host = [], []
@@ -65,8 +69,19 @@ def test_batch_matches_oracle_and_single_calls(torch_dev):
         P.hh_trafo(qq, h, t, nbw)
         singles.append(qq)
     print("batch of", len(probs), "problems", flush=True)
-    P.hh_trafo_batched(probs)
+    P.profile_enable(True)
+    try:
+        P.hh_trafo_batched(probs, batch=batch)
+        pr = P.profile_last()
+    finally:
+        P.profile_enable(False)
     torch.cuda.synchronize()
+    # every problem runs the two-lane kernel: one group per nbw (32 and 64),
+    # each one launch or its diagonal sequence
+    if sched == "one_launch":
+        assert pr["launches"] == 2, pr
+    elif sched == "diagonal":
+        assert pr["launches"] > 2, pr
     for (q, _, _, nbw), (hh, tau, Z), s, (n, _, nev) in zip(probs, host, singles, sizes):
         ref = bt.bt_tridiag_to_band(hh, tau, Z, n, nbw)
         got = q.cpu().numpy()
@@ -160,9 +175,25 @@ def test_batched_workload_sampled(torch_dev):
         norms0.append(torch.linalg.vector_norm(q, dim=0))
         if i in check:
             host[i] = (hh, tau, Z)
+    # single calls of the checked problems, for bitwise comparison
+    singles = {}
+    for i in check:
+        q, h, t, nbw = probs[i]
+        qq = q.clone()
+        P.hh_trafo(qq, h, t, nbw)
+        singles[i] = qq
     print("batched workload: 256 problems", flush=True)
-    P.hh_trafo_batched(probs)
+    P.profile_enable(True)
+    try:
+        P.hh_trafo_batched(probs)
+        pr = P.profile_last()
+    finally:
+        P.profile_enable(False)
     torch.cuda.synchronize()
+    print(f"  one launch: {pr['launches']} launch(es), {pr['kernel_ms']:.2f} ms", flush=True)
+    assert pr["launches"] == 1, pr
+    for i in check:
+        assert torch.equal(probs[i][0], singles[i]), i
     for i, (q, _, _, _) in enumerate(probs):
         rel = ((torch.linalg.vector_norm(q, dim=0) - norms0[i]).abs() / norms0[i]).max().item()
         assert rel < 1e-12, (i, rel)
@@ -170,3 +201,63 @@ def test_batched_workload_sampled(torch_dev):
         n = int(sizes[i])
         ref = bt.bt_tridiag_to_band(hh, tau, Z, n, 32)
         assert checks.max_rel_err(probs[i][0].cpu().numpy(), ref) <= TOL["r64"], i
+
+
+@pytest.mark.parametrize("dt", ["r32", "c64"])
+def test_one_launch_batch_other_dtypes(torch_dev, dt):
+    """fp32 and complex problems of the two-lane kernel: one launch per
+    (dtype, nbw) group, each result bitwise the single call's and within the
+    oracle's bar; problems of uneven n and nev, ragged stripes."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    sizes = [(257, 64, 100), (1000, 64, 33), (70, 64, 70), (400, 64, 65)]
+    probs, host = [], []
+    for i, (n, nbw, nev) in enumerate(sizes):
+        p, h = make(torch, dev, n, nbw, nev, dt, 5000 + i)
+        probs.append(p)
+        host.append(h)
+    singles = []
+    for (q, h, t, nbw) in probs:
+        qq = q.clone()
+        P.hh_trafo(qq, h, t, nbw)
+        singles.append(qq)
+    P.profile_enable(True)
+    try:
+        P.hh_trafo_batched(probs, batch=P.BATCH_ONE_LAUNCH)
+        pr = P.profile_last()
+    finally:
+        P.profile_enable(False)
+    torch.cuda.synchronize()
+    assert pr["path"] == P.PATH_SPLIT and pr["launches"] == 1, pr
+    for (q, _, _, nbw), (hh, tau, Z), s, (n, _, nev) in zip(probs, host, singles, sizes):
+        assert torch.equal(q, s), (n, nev)
+        ref = bt.bt_tridiag_to_band(rounded(hh, dt), rounded(tau, dt), rounded(Z, dt), n, nbw)
+        assert checks.max_rel_err(q.cpu().numpy().astype(ref.dtype), ref) <= TOL[dt]
+
+
+def test_few_large_problems_take_the_diagonal_schedule(torch_dev):
+    """Two large problems have too few stripes to fill the device in one
+    launch: the library's model picks the diagonal sequence, and the result
+    equals the forced single launch bitwise (same per-column arithmetic)."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    sizes = [(3000, 64, 3000), (2500, 64, 1200)]
+    probs, probs2 = [], []
+    for i, (n, nbw, nev) in enumerate(sizes):
+        p, _ = make(torch, dev, n, nbw, nev, "r64", 6000 + i)
+        probs.append(p)
+        probs2.append((p[0].clone(), p[1], p[2], p[3]))
+    P.profile_enable(True)
+    try:
+        P.hh_trafo_batched(probs)
+        auto = P.profile_last()
+        P.hh_trafo_batched(probs2, batch=P.BATCH_ONE_LAUNCH)
+        one = P.profile_last()
+    finally:
+        P.profile_enable(False)
+    torch.cuda.synchronize()
+    print(f"  auto: {auto['launches']} launches {auto['kernel_ms']:.2f} ms; one launch "
+          f"{one['kernel_ms']:.2f} ms", flush=True)
+    assert auto["launches"] > 1 and one["launches"] == 1
+    for a, b in zip(probs, probs2):
+        assert torch.equal(a[0], b[0])

@@ -18,7 +18,7 @@ def test_set_get_size_classes():
     assert P.tuner_size() == 0 and P.tuner_get(P.R64, 64, 20000, 20000) is None
     P.tuner_set(P.R64, 64, 20000, 20000, path=P.PATH_SPLIT, k=64, steps=8, streams=2)
     got = P.tuner_get(P.R64, 64, 20000, 20000)
-    assert got == {"path": P.PATH_SPLIT, "k": 64, "steps": 8, "order": 0, "streams": 2}
+    assert got == {"path": P.PATH_SPLIT, "k": 64, "steps": 8, "order": 0, "streams": 2, "batch": 0}
     # quarter-octave classes: 4 log2(20000) = 57.15, [19504, 23193) shares it
     assert P.tuner_get(P.R64, 64, 21000, 19600) == got
     assert P.tuner_get(P.R64, 64, 24000, 20000) is None

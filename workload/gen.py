@@ -170,27 +170,50 @@ def scf_trace(nseq=64, steps=20, rate=200.0, p32=0.25, seed_arrivals=502, seed_d
     return t - t[0], i % nseq, i // nseq, fp32
 
 
-def device_reflectors(torch, n, b, device, generator, dtype=None):
+def device_reflectors(torch, n, b, device, generator, dtype=None, complex_=False):
     """synthetic_reflectors drawn on the device with a torch generator (same
     structure and distribution, another random stream): for throughput runs
-    whose inputs stand in for an upstream stage that produces them on the
-    GPU.  Returns (hh, tau) 1-D device tensors (fp64 unless dtype)."""
+    and full-size tests whose inputs stand in for an upstream stage that
+    produces them on the GPU.  Returns (hh, tau) 1-D device tensors (fp64,
+    complex128 with complex_, unless dtype)."""
     _, _, _, LL = reflector_layout(n, b)
     N = LL.size
-    dt = dtype or torch.float64
     L = torch.from_numpy(LL).to(device)
+    pad = torch.arange(b, device=device)[None, :] >= L[:, None]
+    if complex_:
+        dt = dtype or torch.complex128
+        h = np.sqrt(0.5) / np.sqrt(b)
+        re = torch.randn((N, b), generator=generator, device=device, dtype=torch.float64) * h
+        im = torch.randn((N, b), generator=generator, device=device, dtype=torch.float64) * h
+        hh = torch.complex(re, im)
+        del re, im
+        hh[:, 0] = 1.0
+        hh.masked_fill_(pad, 0.0)
+        nrm2 = (hh.real * hh.real + hh.imag * hh.imag).sum(dim=1)
+        th = torch.rand(N, generator=generator, device=device, dtype=torch.float64) * (2 * np.pi)
+        tau = (1.0 - torch.polar(torch.ones_like(th), th)) / nrm2
+        return hh.reshape(-1).to(dt), tau.to(dt)
+    dt = dtype or torch.float64
     hh = torch.randn((N, b), generator=generator, device=device, dtype=torch.float64)
     hh *= 1.0 / np.sqrt(b)
     hh[:, 0] = 1.0
-    hh.masked_fill_(torch.arange(b, device=device)[None, :] >= L[:, None], 0.0)
+    hh.masked_fill_(pad, 0.0)
     tau = 2.0 / (hh * hh).sum(dim=1)
     tau.masked_fill_(L == 1, 0.0)
     return hh.reshape(-1).to(dt), tau.to(dt)
 
 
-def device_block(torch, n, nev, device, generator, dtype=None):
+def device_block(torch, n, nev, device, generator, dtype=None, complex_=False):
     """gaussian_block drawn on the device: column-major (n, nev) tensor with
-    N(0, 1/n) entries (fp64 unless dtype)."""
+    N(0, 1/n) entries (complex: each part N(0, 1/(2n))); fp64 / complex128
+    unless dtype."""
+    if complex_:
+        h = np.sqrt(0.5) / np.sqrt(n)
+        re = torch.randn((nev, n), generator=generator, device=device, dtype=torch.float64) * h
+        im = torch.randn((nev, n), generator=generator, device=device, dtype=torch.float64) * h
+        z = torch.complex(re, im)
+        del re, im
+        return z.to(dtype or torch.complex128).t()
     z = torch.randn((nev, n), generator=generator, device=device, dtype=torch.float64)
     z *= 1.0 / np.sqrt(n)
     return z.to(dtype or torch.float64).t()
