@@ -66,7 +66,9 @@ enum {
     ELPA_ERR_ALIGN = -3,  /* pointer not aligned to the element size */
     ELPA_ERR_NOMEM = -4,  /* device workspace could not be allocated (nothing enqueued) */
     ELPA_ERR_DEVICE = -5, /* HIP launch or runtime failure */
-    ELPA_ERR_PLAN = -6    /* explicit plan not valid for this problem (or a field out of range) */
+    ELPA_ERR_PLAN = -6,   /* explicit plan not valid for this problem (or a field out of range) */
+    ELPA_ERR_ADMIT = -7   /* the problem's workspace exceeds the memory the call may use
+                             (the fixed scratch of elpa_hh_trafo_noalloc) */
 };
 
 /* kernel family selection */
@@ -199,6 +201,32 @@ typedef struct {
  */
 int elpa_hh_trafo_batched(const elpa_hh_problem *probs, int64_t count, void *stream,
                           const elpa_hh_plan *plan);
+
+/*
+ * Allocation-free variant of elpa_hh_trafo, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same operation, arguments, layouts and validation
+ * as elpa_hh_trafo.  The two-lane stripe kernel (the library default, nbw 32
+ * or 64) runs entirely on the caller's stream with its workspace (the
+ * stripe-major copy of Q and the packed reflectors) in a fixed device array of
+ * ELPA_HH_NOALLOC_SCRATCH_BYTES per device, which the library holds from load
+ * until the process ends; nbw without a two-lane kernel runs the reference
+ * kernel, which needs no workspace.  No device memory is allocated or freed
+ * and no tuned plan is consulted (the library's default k for (dtype, nbw);
+ * 1 stripe group).
+ * Limit: a problem whose workspace (elpa_hh_workspace_bytes with plan
+ * {ELPA_PATH_SPLIT, 0, 0, 0, 1, 0}) exceeds ELPA_HH_NOALLOC_SCRATCH_BYTES is
+ * refused with ELPA_ERR_ADMIT, nothing enqueued (fp64 up to about
+ * n = nev = 4400).
+ * Every call on a device shares that device's scratch, which keeps the last
+ * call's contents (each call writes every scratch byte it reads first):
+ * calls that overlap on one device, from different streams or threads, RACE
+ * and give wrong results; serialise them (one stream, or events).
+ */
+#define ELPA_HH_NOALLOC_SCRATCH_BYTES (256u << 20)
+int elpa_hh_trafo_noalloc(int64_t n, int64_t nev, int64_t nbw, const void *hh,
+                          const void *tau, void *Q, int64_t ldq, int32_t dtype,
+                          void *stream);
 
 /*
  * Device workspace (bytes) that elpa_hh_trafo_plan allocates, in stream order,

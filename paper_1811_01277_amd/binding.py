@@ -57,6 +57,8 @@ def library():
         L.elpa_hh_trafo.restype = C.c_int
         L.elpa_hh_trafo_plan.argtypes = [i64, i64, i64, p, p, p, i64, i32, p, C.POINTER(_Plan)]
         L.elpa_hh_trafo_plan.restype = C.c_int
+        L.elpa_hh_trafo_noalloc.argtypes = [i64, i64, i64, p, p, p, i64, i32, p]
+        L.elpa_hh_trafo_noalloc.restype = C.c_int
         L.elpa_hh_trafo_batched.argtypes = [C.POINTER(_Problem), i64, p, C.POINTER(_Plan)]
         L.elpa_hh_trafo_batched.restype = C.c_int
         L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
@@ -255,6 +257,18 @@ def hh_trafo_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0, path=None, k=0, 
     return int(library().elpa_hh_trafo_plan(
         n, nev, nbw, C.c_void_p(hh), C.c_void_p(tau), C.c_void_p(q), ldq, dtype,
         C.c_void_p(stream), C.byref(pl) if pl is not None else None))
+
+
+# fixed device scratch of the allocation-free entry point (include/elpa_hh.h)
+NOALLOC_SCRATCH_BYTES = 256 << 20
+
+
+def hh_trafo_noalloc_ptr(n, nev, nbw, hh, tau, q, ldq, dtype, stream=0):
+    """Raw-pointer allocation-free entry (elpa_hh_trafo_noalloc): returns the
+    library's status code (no raise)."""
+    return int(library().elpa_hh_trafo_noalloc(
+        n, nev, nbw, C.c_void_p(hh), C.c_void_p(tau), C.c_void_p(q), ldq, dtype,
+        C.c_void_p(stream)))
 
 
 def _dtype_code(t):

@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "libelpahip.so")
 SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_stripe_r64.hip",
            "hh_stripe_r32.hip", "hh_stripe_c64.hip", "hh_split.hip", "hh_split_r64.hip",
            "hh_split_r32.hip", "hh_split_c64.hip", "hh_wy.hip", "bt2.hip", "b2t.hip", "f2b.hip",
-           "gen.hip", "dc.hip"]
+           "gen.hip", "dc.hip", "hh_noalloc.hip"]
 ARCH = os.environ.get("ELPA_HIP_ARCH", "gfx950")
 
 FLAGS = [

@@ -302,6 +302,41 @@ int elpa_hh_trafo(int64_t n, int64_t nev, int64_t nbw, const void* hh, const voi
   return elpa_hh_trafo_plan(n, nev, nbw, hh, tau, Q, ldq, dtype, stream, nullptr);
 }
 
+int elpa_hh_trafo_noalloc(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau,
+                          void* Q, int64_t ldq, int32_t dtype, void* stream) {
+  int rc = validate(n, nev, nbw, hh, tau, Q, ldq, dtype);
+  if (rc != ELPA_OK) return rc;
+  if (n <= 1 || nev == 0) return ELPA_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  // the library's default two-lane kernel, one stripe group on the caller's
+  // stream; no tuner lookup (a tuned plan may name a family without a
+  // caller-workspace form)
+  const elpa_hh_plan split{ELPA_PATH_SPLIT, 0, 0, 0, 1, 0};
+  int path = 0;
+  const ehh::StripeEntry* se = resolve(dtype, nbw, &split, &path, &rc);
+  // no timing events are created or recorded on this path
+  ehh::ProfState& prof = ehh::prof_state();
+  const bool prof_on = prof.on;
+  prof.on = false;
+  hipError_t err;
+  if (rc != ELPA_OK || !se || !se->with_ws) {
+    // no two-lane kernel for this nbw: the reference kernel works in place
+    err = ehh::ref_launcher(dtype)(hh, tau, Q, ldq, n, nev, nbw, st);
+  } else {
+    void* ws = nullptr;
+    size_t cap = 0;
+    err = ehh::noalloc_scratch(&ws, &cap);
+    if (err == hipSuccess && se->workspace(n, nev) > cap) {
+      prof.on = prof_on;
+      return ELPA_ERR_ADMIT;
+    }
+    if (err == hipSuccess)
+      err = se->with_ws(hh, tau, Q, ldq, n, nev, tile_opts(&split), st, device_cus(), ws);
+  }
+  prof.on = prof_on;
+  return status_of(err);
+}
+
 int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dtype,
                                 const elpa_hh_plan* plan) {
   if (n < 0 || nev < 0 || nbw < 1 || elem_size(dtype) == 0) return -1;
@@ -389,6 +424,8 @@ const char* elpa_strerror(int code) {
     case ELPA_ERR_NOMEM: return "device workspace allocation failed";
     case ELPA_ERR_DEVICE: return "HIP launch or runtime failure";
     case ELPA_ERR_PLAN: return "explicit plan cannot run this problem";
+    case ELPA_ERR_ADMIT:
+      return "the problem's workspace exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown error code";
   }
 }

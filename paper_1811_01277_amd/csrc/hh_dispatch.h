@@ -54,6 +54,10 @@ const StripeEntry* split_table(int* size);   // two lanes per column, packed ref
 const StripeEntry* wy_table(int* size);      // compact-WY sub-groups on MFMA
 RefLaunch ref_launcher(int dtype);
 
+// Device address and size of the current device's fixed scratch (the
+// allocation-free entry point's workspace; hh_noalloc.hip).
+hipError_t noalloc_scratch(void** out, size_t* bytes);
+
 // Tuned plan of the size class of (n, nev), if the tuner holds one.
 bool tuner_lookup(int32_t dtype, int64_t nbw, int64_t n, int64_t nev, elpa_hh_plan* out);
 
