@@ -70,8 +70,11 @@ def parse():
     ap.add_argument("--batched-only", action="store_true",
                     help="instead of the benchmark: only the batched workload leg (for profiling "
                          "it on its own)")
-    ap.add_argument("--served-rates", default="120,250",
-                    help="Poisson arrival rates of the served stream (requests / s)")
+    ap.add_argument("--served-rates", default="",
+                    help="Poisson arrival rates of the served stream (requests / s; default "
+                         "0.8x and 1.25x the plain path's measured capacity)")
+    ap.add_argument("--served-only", action="store_true",
+                    help="instead of the benchmark: only the served stream leg")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark: copy a MIB-MiB device buffer 3 times "
                          "(reference kernel of known size for the HBM byte counters)")
@@ -80,20 +83,32 @@ def parse():
 
 def served_stream(args):
     """The served SCF stream: 64 sequences x 20 solves, n_q ~ U{1000..6000},
-    nbw 64, nev = n, Poisson arrivals (rates below), each
-    request fp32 with probability 0.25.  Each sequence keeps its Q, reflectors
+    nbw 64, nev = n, Poisson arrivals.  Each sequence keeps its Q, reflectors
     and tau (fp64 and fp32) resident; they are drawn on the device
     (workload.device_*; the upstream stages that would produce them are not
-    timed).  The same trace is served with continuous batching and by the
-    plain one-call-at-a-time path, at each rate of args.served_rates (one
-    below the plain path's capacity, one above it)."""
+    timed).
+
+    * capacity: the plain one-call-at-a-time path with every request ready at
+      once (solves/s);
+    * the mixed trace (each request fp32 with probability 0.25) served with
+      continuous batching and by the plain path at 0.8x and 1.25x that
+      capacity (or at args.served_rates if given);
+    * precision switching (the paper's single precision for the first SCF
+      steps, double for the rest): fp32 for the first 5 of each sequence's 20
+      steps, then fp64, against the same arrivals all in fp64, both served
+      and plain, at 0.8x capacity (and served at 1.25x, where the switch
+      shows in throughput); a sample of sequences' fp64 buffers are
+      checked against the oracle after the served run, and one fresh fp32
+      request per sampled sequence is compared with the fp64 oracle."""
     import torch
     import workload as W
+    from concurrent.futures import ThreadPoolExecutor
+    from oracle import bt, checks
     from paper_1811_01277_amd.serve import Request, Server, latency_stats, run_plain
+    import paper_1811_01277_amd as P
     dev = torch.device("cuda:0")
-    nseq, steps = 64, 20
+    nseq, steps, switch = 64, 20, 5
     sizes = W.scf_sequence_sizes(nseq, 1000, 6000, seed=501)
-    rates = [float(x) for x in args.served_rates.split(",") if x]
     g = torch.Generator(device=dev)
     g.manual_seed(510000)
     state = []
@@ -104,8 +119,8 @@ def served_stream(args):
         state.append({"r64": (Z, hh, tau), "r32": (Z.t().float().t(), hh.float(), tau.float())})
     torch.cuda.synchronize()
 
-    def requests(rate):
-        t, sq, st, f32 = W.scf_trace(nseq, steps, rate=rate, p32=0.25)
+    def requests(rate, switch_step=None, p32=0.25):
+        t, sq, st, f32 = W.scf_trace(nseq, steps, rate=rate, p32=p32, switch_step=switch_step)
         out, last = [], {}
         for i in range(len(t)):
             q = int(sq[i])
@@ -119,18 +134,96 @@ def served_stream(args):
     for r in warm:
         r.arrival, r.after = 0.0, -1
     Server(dev, slots=3, max_batch=32).run(warm)
+    cap = latency_stats(run_plain(requests(1e9), dev))["solves_per_s"]
+    if args.served_rates:
+        rates = [float(x) for x in args.served_rates.split(",") if x]
+    else:
+        rates = [round(0.8 * cap, 1), round(1.25 * cap, 1)]
     runs = []
     for rate in rates:
         srv = Server(dev, slots=3, max_batch=32)
         served = latency_stats(srv.run(requests(rate)))
         plain = latency_stats(run_plain(requests(rate), dev))
-        runs.append({"rate_per_s": rate, "served": served, "plain": plain,
+        runs.append({"rate_per_s": rate, "rate_vs_plain_capacity": round(rate / cap, 3),
+                     "served": served, "plain": plain,
                      "solves_per_s_vs_plain": round(served["solves_per_s"] /
                                                     plain["solves_per_s"], 3),
+                     "p99_vs_plain": round(served["p99_ms"] / plain["p99_ms"], 3),
                      "batches": len(srv.batches)})
+    # precision switching at 0.8x capacity; sampled sequences' fp64 buffers
+    # checked against the oracle after the served run (each holds its input
+    # with one reflector application per fp64 request of the trace)
+    rate = round(0.8 * cap, 1)
+    sample = sorted({int(np.argmin(sizes)), int(np.argmax(sizes)), 7, 33})
+    cols = [0, 1]
+    before = {q: state[q]["r64"][0][:, cols].cpu().numpy() for q in sample}
+    sw_reqs = requests(rate, switch_step=switch)
+    Server(dev, slots=3, max_batch=32).run(sw_reqs)
+    sw_served = latency_stats(sw_reqs)
+    after = {q: state[q]["r64"][0][:, cols].cpu().numpy() for q in sample}
+    n64 = {q: sum(1 for r in sw_reqs if r.seq == q and r.q.dtype == torch.float64)
+           for q in sample}
+    sw_plain = latency_stats(run_plain(requests(rate, switch_step=switch), dev))
+    all64_served = latency_stats(Server(dev, slots=3, max_batch=32).run(
+        requests(rate, switch_step=0)))
+    all64_plain = latency_stats(run_plain(requests(rate, switch_step=0), dev))
+    # above capacity the switch shows in throughput: fp32 steps finish sooner
+    hi = round(1.25 * cap, 1)
+    sw_hi = latency_stats(Server(dev, slots=3, max_batch=32).run(
+        requests(hi, switch_step=switch)))
+    all64_hi = latency_stats(Server(dev, slots=3, max_batch=32).run(
+        requests(hi, switch_step=0)))
+    host = {q: (state[q]["r64"][1].cpu().numpy(), state[q]["r64"][2].cpu().numpy())
+            for q in sample}
+
+    def replay(q):
+        n = int(sizes[q])
+        z = before[q]
+        for _ in range(n64[q]):
+            z = bt.bt_tridiag_to_band(host[q][0], host[q][1], z, n, 64, nthreads=1)
+        return q, checks.max_rel_err(after[q], z)
+
+    # fp32 error per request: one fresh fp32 request per sampled sequence
+    g2 = torch.Generator(device=dev)
+    g2.manual_seed(520000)
+    f32_err = {}
+    f32_in = {}
+    for q in sample:
+        n = int(sizes[q])
+        hh, tau = W.device_reflectors(torch, n, 64, dev, g2)
+        Z = W.device_block(torch, n, 4, dev, g2)          # column major, fp64
+        q32 = Z.t().float().t()                            # the fp32 request's Q
+        P.hh_trafo(q32, hh.float(), tau.float(), 64)
+        torch.cuda.synchronize()
+        f32_in[q] = (hh.cpu().numpy(), tau.cpu().numpy(), np.asfortranarray(Z.cpu().numpy()),
+                     q32.cpu().numpy().astype(np.float64))
+    with ThreadPoolExecutor(max_workers=host_threads()) as ex:
+        rep = dict(ex.map(replay, sample))
+        futs = {q: ex.submit(bt.bt_tridiag_to_band, v[0], v[1], v[2], int(sizes[q]), 64, 1)
+                for q, v in f32_in.items()}
+        for q, f in futs.items():
+            f32_err[q] = checks.max_rel_err(f32_in[q][3], f.result())
     return {"workload": f"{nseq} sequences x {steps} solves, n ~ U{{1000..6000}}, nbw 64, "
-                        f"nev = n, Poisson arrivals, 25% fp32; slots 3, max batch 32",
-            "runs": runs}
+                        f"nev = n, Poisson arrivals; slots 3, max batch 32",
+            "plain_capacity_solves_per_s": cap,
+            "runs": runs,
+            "precision_switching": {
+                "trace": f"fp32 for steps 0..{switch - 1} of each sequence, fp64 after; "
+                         f"{rate} requests/s (0.8x plain capacity)",
+                "served": sw_served, "plain": sw_plain,
+                "all_fp64_same_arrivals": {"served": all64_served, "plain": all64_plain},
+                "solves_per_s_switch_vs_all_fp64_served":
+                    round(sw_served["solves_per_s"] / all64_served["solves_per_s"], 3),
+                "above_capacity": {"rate_per_s": hi, "served_switch": sw_hi,
+                                   "served_all_fp64": all64_hi,
+                                   "solves_per_s_switch_vs_all_fp64":
+                                       round(sw_hi["solves_per_s"] / all64_hi["solves_per_s"], 3)},
+                "fp64_buffers_vs_oracle": {
+                    str(q): {"n": int(sizes[q]), "fp64_applications": n64[q],
+                             "max_rel_err": float(f"{rep[q]:.3e}")} for q in sample},
+                "fp32_request_err_vs_fp64_oracle": {
+                    str(q): {"n": int(sizes[q]), "max_rel_err": float(f"{f32_err[q]:.3e}")}
+                    for q in sample}}}
 
 
 def batched_workload(quick=False):
@@ -631,6 +724,9 @@ def main():
         print(json.dumps({"solve": solve_leg(args)}), flush=True)
         if not args.no_gen:
             print(json.dumps({"generalized": gen_leg(args)}), flush=True)
+        return
+    if args.served_only:
+        print(json.dumps({"served_stream": served_stream(args)}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched_workload": batched_workload(quick=True)}), flush=True)

@@ -20,15 +20,19 @@ computation runs in the HIP library):
   one elpa_hh_trafo_batched call, so requests that arrive while others run
   are admitted as soon as a slot and memory free up and their work overlaps
   on the device;
-* a lone request on an otherwise idle device runs as a single call with the
-  library's stripe-group streams (the batched call keeps to its slot's
-  stream, so concurrent slots never share the library's streams);
+* a batch of one request runs as a single call with the library's plan and
+  stripe-group streams (each slot stream forks onto library streams of its
+  own); larger batches run as one elpa_hh_trafo_batched call;
 * completion is tracked with events; a solve that depends on an earlier one
   (the next step of the same SCF sequence) becomes ready when that completes.
 
-Latency of a request = completion - max(arrival, completion of the solve it
-depends on).  `run_plain` serves the same requests one call at a time on one
-stream, as the baseline.
+Times: arrivals and readiness on the host clock of the trace; completion is
+the device time of an event recorded behind the request's work, placed on the
+same clock through an event recorded at the trace start (so the poll loop's
+granularity does not bias it).  Latency of a request = completion -
+max(arrival, completion of the solve it depends on).  `run_plain` serves the
+same requests one call at a time on one stream, as the baseline, timed the
+same way.
 """
 import time
 from dataclasses import dataclass
@@ -63,12 +67,35 @@ def _dtype_code(q):
 
 
 def footprint(r):
-    """Library workspace bytes of one request in a batched call (the sum over a
-    batch bounds the batch's workspace)."""
+    """Library workspace bytes of one request, alone (a single call with the
+    library's plan) or in a batched call with the library's plan, whichever is
+    larger: the sum over a batch bounds what its launch allocates."""
     if getattr(r, "_fp", None) is None:
         n, nev = r.q.shape
-        r._fp = max(0, B.workspace_bytes_batched([(n, nev, r.nbw, _dtype_code(r.q))]))
+        dt = _dtype_code(r.q)
+        r._fp = max(0, B.workspace_bytes(n, nev, r.nbw, dt),
+                    B.workspace_bytes_batched([(n, nev, r.nbw, dt)]))
     return r._fp
+
+
+class _Clock:
+    """Device event times on the trace's host clock: an event recorded on an
+    idle device at t0 = 0."""
+
+    def __init__(self, torch, device):
+        torch.cuda.synchronize(device)
+        self.e0 = torch.cuda.Event(enable_timing=True)
+        self.e0.record(torch.cuda.current_stream(device))
+        torch.cuda.synchronize(device)
+        self.t0 = time.perf_counter()
+
+    def now(self):
+        return time.perf_counter() - self.t0
+
+    def at(self, ev):
+        """Time of a completed event: its device time after e0, but never
+        later than now (the host time at which its completion is observed)."""
+        return min(self.e0.elapsed_time(ev) * 1e-3, self.now())
 
 
 class Server:
@@ -94,20 +121,20 @@ class Server:
         pending = sorted(requests, key=lambda r: r.arrival)
         done_at = {}
         waiting, ready = [], []
-        busy = [None] * len(self.streams)  # (event, batch, bytes, forked)
+        busy = [None] * len(self.streams)  # (event, batch, bytes)
         in_use = 0
         left = len(pending)
         pi = 0
-        torch.cuda.synchronize(self.device)
-        t0 = time.perf_counter()
+        clock = _Clock(torch, self.device)
         while left:
-            now = time.perf_counter() - t0
+            now = clock.now()
             progress = False
             for i, b in enumerate(busy):
                 if b is not None and b[0].query():
+                    t = clock.at(b[0])
                     for r in b[1]:
-                        r.t_done = now
-                        done_at[r.rid] = now
+                        r.t_done = t
+                        done_at[r.rid] = t
                     in_use -= b[2]
                     left -= len(b[1])
                     busy[i] = None
@@ -145,14 +172,12 @@ class Server:
                     break
                 ready = rest
                 st = self.streams[i]
-                idle = all(x is None for x in busy)
-                if len(batch) == 1 and idle:
+                if len(batch) == 1:
                     r = batch[0]
                     B.hh_trafo(r.q, r.hh, r.tau, r.nbw, stream=st)  # library plan
                 else:
-                    B.hh_trafo_batched([(r.q, r.hh, r.tau, r.nbw) for r in batch], stream=st,
-                                       streams=1)
-                ev = torch.cuda.Event()
+                    B.hh_trafo_batched([(r.q, r.hh, r.tau, r.nbw) for r in batch], stream=st)
+                ev = torch.cuda.Event(enable_timing=True)
                 ev.record(st)
                 for r in batch:
                     r.t_start = now
@@ -174,11 +199,10 @@ def run_plain(requests, device, poll_s=50e-6):
     st = torch.cuda.Stream(device=device)
     order = sorted(requests, key=lambda r: r.arrival)
     done_at = {}
-    torch.cuda.synchronize(device)
-    t0 = time.perf_counter()
+    clock = _Clock(torch, device)
     queue = list(order)
     while queue:
-        now = time.perf_counter() - t0
+        now = clock.now()
         # oldest request whose dependency is met (requests are served in order)
         r = None
         for cand in queue:
@@ -192,8 +216,10 @@ def run_plain(requests, device, poll_s=50e-6):
         r.t_ready = max(r.arrival, done_at.get(r.after, 0.0))
         r.t_start = now
         B.hh_trafo(r.q, r.hh, r.tau, r.nbw, stream=st)
-        st.synchronize()
-        r.t_done = time.perf_counter() - t0
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(st)
+        ev.synchronize()
+        r.t_done = clock.at(ev)
         done_at[r.rid] = r.t_done
     return requests
 

@@ -107,3 +107,73 @@ def test_memory_budget_limits_inflight_work(torch_dev):
     assert srv.max_busy == 1 and all(b[1] == 1 for b in srv.batches)
     assert srv.max_in_use <= max(fps)
     assert all(r.t_done is not None for r in reqs)
+
+
+def test_scf_precision_switching_through_device_reductions(torch_dev):
+    """An SCF-like stream with precision switching (single precision for the
+    first steps of a sequence, double for the rest), every request derived
+    from its own matrix A_k = A_0 + 1e-3 k (E + E^T) by the device reductions
+    (full -> band, band -> tridiagonal, divide and conquer, all fp64; the
+    fp32 requests get those results rounded), served with continuous
+    batching.  Every result against the oracle on the same reflectors and
+    tridiagonal eigenvectors (fp64: 1e-12; fp32: 5e-5 against the oracle of
+    the rounded inputs, error against the unrounded fp64 oracle printed), and
+    each step's full eigenvectors (band -> full on the device) satisfy
+    A_k Z = Z Lambda to the precision of the request."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    from paper_1811_01277_amd.serve import Request, Server, latency_stats
+    nbw, steps, switch = 32, 4, 2
+    sizes = [200, 260, 330]
+    reqs, meta, last = [], [], {}
+    rid = 0
+    for step in range(steps):
+        for sq, n in enumerate(sizes):
+            A0 = W.sym_gaussian(n, 900 + sq)
+            E = np.random.Generator(np.random.PCG64(950 + sq)).standard_normal((n, n))
+            A = A0 + 1e-3 * step * (E + E.T)
+            a = torch.from_numpy(A.copy()).to(dev).t()       # symmetric: column-major view
+            v, t1 = P.full_to_band(a, nbw)
+            d, e, hh, tau = P.band_to_tridiag(a, nbw)
+            lam, z = P.tridiag_eigh(d, e, n)
+            torch.cuda.synchronize()
+            f32 = step < switch
+            host = (hh.cpu().numpy(), tau.cpu().numpy(), np.asfortranarray(z.cpu().numpy()))
+            if f32:
+                q, h, ta = z.t().float().t(), hh.float(), tau.float()
+            else:
+                q, h, ta = z.t().contiguous().t(), hh, tau
+            r = Request(rid=rid, q=q, hh=h, tau=ta, nbw=nbw, arrival=0.0,
+                        after=last.get(sq, -1), seq=sq, step=step)
+            last[sq] = rid
+            reqs.append(r)
+            meta.append((A, host, v, t1, lam, f32, n))
+            rid += 1
+    srv = Server(dev, slots=3, max_batch=8)
+    srv.run(reqs)
+    torch.cuda.synchronize()
+    print("switching stream", latency_stats(reqs), "batches", srv.batches, flush=True)
+    for r, (A, (hh, tau, z), v, t1, lam, f32, n) in zip(reqs, meta):
+        got = r.q.cpu().numpy().astype(np.float64)
+        ref64 = bt.bt_tridiag_to_band(hh, tau, z, n, nbw)
+        if f32:
+            rd = lambda x: x.astype(np.float32).astype(np.float64)
+            ref = bt.bt_tridiag_to_band(rd(hh), rd(tau), rd(z), n, nbw)
+            err = checks.max_rel_err(got, ref)
+            print(f"  seq {r.seq} step {r.step} fp32: {err:.2e} vs rounded-input oracle, "
+                  f"{checks.max_rel_err(got, ref64):.2e} vs fp64 oracle", flush=True)
+            assert err <= 5e-5
+        else:
+            assert checks.max_rel_err(got, ref64) <= 1e-12
+        # the request's band eigenvectors to the full matrix's on the device
+        if f32:
+            P.bt2_trafo(r.q, v.float(), t1.float(), nbw)
+        else:
+            P.bt2_trafo(r.q, v, t1, nbw)
+        torch.cuda.synchronize()
+        Z = r.q.cpu().numpy().astype(np.float64)
+        lamh = lam.cpu().numpy()
+        R = A @ Z - Z * lamh[None, :]
+        eps = 2.0 ** -24 if f32 else 2.0 ** -52
+        ratio = np.abs(R).sum(0).max() / (np.abs(A).sum(0).max() * n * eps)
+        assert ratio < 50, (r.seq, r.step, f32, ratio)
