@@ -139,17 +139,28 @@ def served_stream(args):
         rates = [float(x) for x in args.served_rates.split(",") if x]
     else:
         rates = [round(0.8 * cap, 1), round(1.25 * cap, 1)]
+    # per-sequence graphs of prepared batches (setup, not timed)
+    gsrv = Server(dev, slots=3, max_batch=32)
+    t0 = time.perf_counter()
+    gbytes = gsrv.prepare_graphs(requests(1e9))
+    gsetup = time.perf_counter() - t0
     runs = []
     for rate in rates:
         srv = Server(dev, slots=3, max_batch=32)
         served = latency_stats(srv.run(requests(rate)))
+        gsrv.batches, gsrv.replays = [], 0
+        with_graphs = latency_stats(gsrv.run(requests(rate)))
         plain = latency_stats(run_plain(requests(rate), dev))
         runs.append({"rate_per_s": rate, "rate_vs_plain_capacity": round(rate / cap, 3),
-                     "served": served, "plain": plain,
+                     "served": served, "served_graphs": with_graphs, "plain": plain,
                      "solves_per_s_vs_plain": round(served["solves_per_s"] /
                                                     plain["solves_per_s"], 3),
                      "p99_vs_plain": round(served["p99_ms"] / plain["p99_ms"], 3),
-                     "batches": len(srv.batches)})
+                     "graphs_solves_per_s_vs_plain": round(with_graphs["solves_per_s"] /
+                                                           plain["solves_per_s"], 3),
+                     "graphs_p99_vs_plain": round(with_graphs["p99_ms"] / plain["p99_ms"], 3),
+                     "batches": len(srv.batches), "graph_replays": gsrv.replays})
+    gsrv.close_graphs()
     # precision switching at 0.8x capacity; sampled sequences' fp64 buffers
     # checked against the oracle after the served run (each holds its input
     # with one reflector application per fp64 request of the trace)
@@ -206,6 +217,8 @@ def served_stream(args):
     return {"workload": f"{nseq} sequences x {steps} solves, n ~ U{{1000..6000}}, nbw 64, "
                         f"nev = n, Poisson arrivals; slots 3, max batch 32",
             "plain_capacity_solves_per_s": cap,
+            "graphs": {"prepared_batches": 2 * nseq, "device_bytes": gbytes,
+                       "setup_s": round(gsetup, 2)},
             "runs": runs,
             "precision_switching": {
                 "trace": f"fp32 for steps 0..{switch - 1} of each sequence, fp64 after; "

@@ -229,6 +229,38 @@ int elpa_hh_trafo_noalloc(int64_t n, int64_t nev, int64_t nbw, const void *hh,
                           void *stream);
 
 /*
+ * Prepared batched call, so that a batched back-transformation can be
+ * captured into a HIP graph and replayed (a served SCF sequence repeats the
+ * same call on the same buffers at every step).  elpa_hh_trafo_batched
+ * stages its descriptor tables through host memory and allocates its
+ * workspace on every call; a prepared batch does both once:
+ *
+ * elpa_hh_batch_create: validates the problems and plan exactly as
+ *   elpa_hh_trafo_batched (same codes; a group whose kernel family has no
+ *   prepared form, i.e. other than the two-lane kernel, gives ELPA_ERR_PLAN),
+ *   builds the same schedules, allocates the device workspace and tables on
+ *   the current device (hipMalloc; ELPA_ERR_NOMEM if it cannot) and copies the
+ *   tables there before returning (synchronous).  A single problem is
+ *   prepared as the single-problem call (its stripe groups on library streams
+ *   forked from the run's stream).  probs is read during the call; the
+ *   problems' device pointers are kept and must stay valid until destroy.
+ * elpa_hh_batch_run: the back-transformation of every problem of the batch
+ *   on `stream`, with the results of elpa_hh_trafo_batched (bitwise, same
+ *   kernels and schedule): kernel launches and event fork/join only, no
+ *   allocation, no copy, no host synchronisation, so it may be captured into
+ *   a graph.  Runs of one batch share its workspace: they must not overlap
+ *   (one stream, or ordered by events).  ELPA_ERR_ARG on another device.
+ * elpa_hh_batch_bytes: device bytes the batch holds.
+ * elpa_hh_batch_destroy: frees it (the caller makes sure no run is pending).
+ */
+typedef struct elpa_hh_batch elpa_hh_batch;
+int elpa_hh_batch_create(const elpa_hh_problem *probs, int64_t count, const elpa_hh_plan *plan,
+                         elpa_hh_batch **out);
+int elpa_hh_batch_run(elpa_hh_batch *batch, void *stream);
+int64_t elpa_hh_batch_bytes(const elpa_hh_batch *batch);
+int elpa_hh_batch_destroy(elpa_hh_batch *batch);
+
+/*
  * Device workspace (bytes) that elpa_hh_trafo_plan allocates, in stream order,
  * for one problem under `plan` (NULL = library choice): the stripe-major copy
  * of Q and, for paths 3 and 4, the packed reflectors.  0 for no-ops and the

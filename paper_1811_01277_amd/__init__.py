@@ -9,7 +9,7 @@ There is no CPU fallback: if the library is missing, import of the binding
 functions raises.
 """
 from .binding import (  # noqa: F401
-    AUTOTUNE_FAST, AUTOTUNE_MEDIUM, Autotune,
+    AUTOTUNE_FAST, AUTOTUNE_MEDIUM, Autotune, Batch,
     BATCH_AUTO, BATCH_DIAGONAL, BATCH_ONE_LAUNCH, C64, ORDER_AUTO, ORDER_LINEAR, ORDER_XCD, PATH_AUTO, PATH_REF, PATH_SPLIT, PATH_STRIPE, PATH_WY,
     R32, R64, ElpaError, band_to_tridiag, bt2_trafo, full_to_band, cholesky_inverse,
     generalized_to_standard, generalized_back, tridiag_eigh, eigenvectors,

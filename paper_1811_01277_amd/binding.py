@@ -59,6 +59,15 @@ def library():
         L.elpa_hh_trafo_plan.restype = C.c_int
         L.elpa_hh_trafo_noalloc.argtypes = [i64, i64, i64, p, p, p, i64, i32, p]
         L.elpa_hh_trafo_noalloc.restype = C.c_int
+        L.elpa_hh_batch_create.argtypes = [C.POINTER(_Problem), i64, C.POINTER(_Plan),
+                                           C.POINTER(C.c_void_p)]
+        L.elpa_hh_batch_create.restype = C.c_int
+        L.elpa_hh_batch_run.argtypes = [p, p]
+        L.elpa_hh_batch_run.restype = C.c_int
+        L.elpa_hh_batch_bytes.argtypes = [p]
+        L.elpa_hh_batch_bytes.restype = i64
+        L.elpa_hh_batch_destroy.argtypes = [p]
+        L.elpa_hh_batch_destroy.restype = C.c_int
         L.elpa_hh_trafo_batched.argtypes = [C.POINTER(_Problem), i64, p, C.POINTER(_Plan)]
         L.elpa_hh_trafo_batched.restype = C.c_int
         L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
@@ -381,6 +390,49 @@ def hh_trafo_batched(problems, stream=None, path=None, k=0, steps=0, order=0, st
     if rc != 0:
         raise ElpaError(rc, strerror(rc))
     return problems
+
+
+class Batch:
+    """A prepared batched call (elpa_hh_batch_*): the schedule, workspace and
+    descriptor tables of a list of (q, hh, tau, nbw) problems are set up once;
+    run() then only launches kernels, so it can be captured into a CUDA/HIP
+    graph (torch.cuda.graph) and replayed.  The tensors must stay alive (and
+    in place) as long as the Batch.  Runs of one Batch must not overlap."""
+
+    def __init__(self, problems, path=None, k=0, steps=0, order=0, streams=0, batch=0):
+        arr, _ = _marshal_batch(problems, 0)
+        pl = _plan(path, k, steps, order, streams, batch)
+        h = C.c_void_p()
+        _check(library().elpa_hh_batch_create(arr, len(problems),
+                                               C.byref(pl) if pl is not None else None,
+                                               C.byref(h)))
+        self._h = h
+        self._keep = list(problems)      # the device buffers the batch points to
+
+    @property
+    def nbytes(self):
+        return int(library().elpa_hh_batch_bytes(self._h))
+
+    def run(self, stream=None):
+        import torch
+        if stream is None:
+            st = torch.cuda.current_stream().cuda_stream
+        elif isinstance(stream, int):
+            st = stream
+        else:
+            st = stream.cuda_stream
+        _check(library().elpa_hh_batch_run(self._h, C.c_void_p(st)))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            library().elpa_hh_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tune_batched(problems, level=0, stream=None):

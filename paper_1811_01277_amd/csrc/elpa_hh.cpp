@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <map>
+#include <memory>
 #include <utility>
 #include <vector>
 
@@ -190,6 +191,15 @@ void prof_begin_call(int path) {
 
 }  // namespace
 
+// A prepared batched call: per kernel group its device workspace and tables;
+// problems of the reference kernel, which needs none, are kept as arguments.
+struct elpa_hh_batch {
+  int dev = -1;
+  int path = ELPA_PATH_AUTO;  // reported by the profile when there is one group
+  std::vector<std::unique_ptr<ehh::PreparedGroup>> groups;
+  std::vector<elpa_hh_problem> singles;
+};
+
 namespace ehh {
 ProfState& prof_state() {
   static thread_local ProfState s;
@@ -294,6 +304,94 @@ int elpa_hh_trafo_batched(const elpa_hh_problem* probs, int64_t count, void* str
     prof.after(st);
     if (err != hipSuccess) return status_of(err);
   }
+  return ELPA_OK;
+}
+
+int elpa_hh_batch_create(const elpa_hh_problem* probs, int64_t count, const elpa_hh_plan* plan,
+                         elpa_hh_batch** out) {
+  if (!out) return ELPA_ERR_ARG;
+  *out = nullptr;
+  if (count < 0 || (count > 0 && !probs)) return ELPA_ERR_ARG;
+  if (plan && (plan->path < ELPA_PATH_AUTO || plan->path > ELPA_PATH_WY)) return ELPA_ERR_PLAN;
+  for (int64_t i = 0; i < count; ++i) {
+    const elpa_hh_problem& p = probs[i];
+    const int rc = validate(p.n, p.nev, p.nbw, p.hh, p.tau, p.Q, p.ldq, p.dtype);
+    if (rc != ELPA_OK) return rc;
+  }
+  // the same grouping as elpa_hh_trafo_batched; every group needs a prepared form
+  std::vector<const ehh::StripeEntry*> order;
+  std::map<const ehh::StripeEntry*, std::vector<int64_t>> groups;
+  auto b = std::make_unique<elpa_hh_batch>();
+  if (hipGetDevice(&b->dev) != hipSuccess) return ELPA_ERR_DEVICE;
+  int last_path = ELPA_PATH_REF;
+  for (int64_t i = 0; i < count; ++i) {
+    const elpa_hh_problem& p = probs[i];
+    elpa_hh_plan tuned{};
+    const elpa_hh_plan* pp = effective_plan(p.dtype, p.nbw, p.n, p.nev, plan, &tuned);
+    int path = 0, rc = 0;
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, pp, &path, &rc, true);
+    if (rc != ELPA_OK) return rc;
+    if (p.n <= 1 || p.nev == 0) continue;
+    last_path = path;
+    if (se) {
+      if (!se->prepare) return ELPA_ERR_PLAN;
+      if (!groups.count(se)) order.push_back(se);
+      groups[se].push_back(i);
+    } else {
+      b->singles.push_back(p);
+    }
+  }
+  b->path = groups.size() + b->singles.size() == 1 ? last_path : ELPA_PATH_AUTO;
+  const int cus = device_cus();
+  for (const ehh::StripeEntry* se : order) {
+    const std::vector<int64_t>& ids = groups[se];
+    ehh::PreparedGroup* g = nullptr;
+    const hipError_t err = se->prepare(probs, ids.data(), (int64_t)ids.size(), tile_opts(plan),
+                                       cus, &g);
+    if (err != hipSuccess) return status_of(err);
+    b->groups.emplace_back(g);
+  }
+  *out = b.release();
+  return ELPA_OK;
+}
+
+int elpa_hh_batch_run(elpa_hh_batch* b, void* stream) {
+  if (!b) return ELPA_ERR_ARG;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return ELPA_ERR_DEVICE;
+  if (dev != b->dev) return ELPA_ERR_ARG;
+  if (b->groups.empty() && b->singles.empty()) return ELPA_OK;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  prof_begin_call(b->path);
+  for (auto& g : b->groups) {
+    const hipError_t err = g->run(st);
+    if (err != hipSuccess) return status_of(err);
+  }
+  for (const elpa_hh_problem& p : b->singles) {
+    ehh::ProfScope prof(st, 0, 0);
+    prof.before(st);
+    const hipError_t err =
+        ehh::ref_launcher(p.dtype)(p.hh, p.tau, p.Q, p.ldq, p.n, p.nev, p.nbw, st);
+    prof.after(st);
+    if (err != hipSuccess) return status_of(err);
+  }
+  return ELPA_OK;
+}
+
+int64_t elpa_hh_batch_bytes(const elpa_hh_batch* b) {
+  if (!b) return -1;
+  int64_t s = 0;
+  for (const auto& g : b->groups) s += (int64_t)g->bytes();
+  return s;
+}
+
+int elpa_hh_batch_destroy(elpa_hh_batch* b) {
+  if (!b) return ELPA_OK;
+  int cur = -1;
+  const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != b->dev && b->dev >= 0;
+  if (switch_dev) (void)hipSetDevice(b->dev);
+  delete b;
+  if (switch_dev) (void)hipSetDevice(cur);
   return ELPA_OK;
 }
 

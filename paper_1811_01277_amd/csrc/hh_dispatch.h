@@ -29,6 +29,17 @@ using BatchedLaunch = hipError_t (*)(const elpa_hh_problem* probs, const int64_t
                                      int64_t cnt, TileOpts opt, hipStream_t st, int num_cu);
 // Device workspace one problem's call allocates (bytes).
 using WorkspaceFn = size_t (*)(int64_t n, int64_t nev);
+// A prepared batched group (elpa_hh_batch_create): device workspace and
+// tables owned for the object's lifetime; run() only launches kernels.
+class PreparedGroup {
+ public:
+  virtual ~PreparedGroup() = default;
+  virtual hipError_t run(hipStream_t st) = 0;
+  virtual size_t bytes() const = 0;  // device bytes owned
+};
+using PrepareFn = hipError_t (*)(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
+                                 TileOpts opt, int num_cu, PreparedGroup** out);
+
 // Same as StripeLaunch on a caller-provided device workspace of at least
 // WorkspaceFn(n, nev) bytes (nothing allocated or freed).
 using StripeLaunchWs = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,
@@ -47,6 +58,7 @@ struct StripeEntry {
   BatchedLaunch batched;  // null: no batched form
   WorkspaceFn workspace;
   StripeLaunchWs with_ws;  // null: the family has no caller-workspace form
+  PrepareFn prepare;       // null: the family has no prepared batched form
 };
 
 const StripeEntry* stripe_table(int* size);  // one lane per column

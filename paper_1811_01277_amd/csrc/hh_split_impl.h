@@ -639,6 +639,20 @@ inline BatchModel batch_model(const std::vector<DiagPlan>& plans, int64_t NB, in
   return r;
 }
 
+// Host-side schedule of one batched group: descriptors (device pointers
+// bound later), the diagonal schedule's entries, and the workspace layout
+// [descriptors | entries | per problem: packed area, stripe copy].
+struct SplitBatchPlan {
+  std::vector<ProblemDesc> d;
+  std::vector<DiagEntry> ent;
+  std::vector<int64_t> eoff, etiles;
+  std::vector<size_t> pat, qat, rbytes;
+  size_t dbytes = 0, ebytes = 0, total = 0, tiles = 0, otiles = 0, ptiles = 0, units = 0;
+  int64_t T = 0;
+  int K = 0;
+  bool one_launch = false;
+};
+
 // Batched: problems idx[0..cnt) of probs (element type E, semi-bandwidth NB,
 // validated by the caller).  Two schedules, the one with the smaller modelled
 // time runs (ties and near-ties, within 10 %, go to the single launch):
@@ -649,14 +663,15 @@ inline BatchModel batch_model(const std::vector<DiagPlan>& plans, int64_t NB, in
 //    launch t's tiles of every problem): for a few large problems, which need
 //    the sweep-block parallelism of the diagonal schedule.
 // opt.batch forces one of them; an explicit tile height (opt.steps > 0)
-// selects the diagonal schedule.
-// Packing and layout conversion run before and after as one launch each over
-// every problem.
+// selects the diagonal schedule.  Returns false if there is nothing to do.
 template <typename E, int NB, int K, int OCC, int PD>
-hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
-                                TileOpts opt, hipStream_t st, int num_cu) {
+hipError_t plan_split_batch(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
+                            TileOpts opt, int num_cu, SplitBatchPlan* out) {
   using Gm = SplitGeom<NB, K>;
   static const int64_t slots = wave_slots(k_split_b<E, NB, K, OCC, PD>, num_cu);
+  SplitBatchPlan& B = *out;
+  B = SplitBatchPlan{};
+  B.K = K;
   std::vector<int64_t> live;
   int64_t total_cols = 0;
   for (int64_t i = 0; i < cnt; ++i) {
@@ -684,17 +699,17 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
     plans.emplace_back(p.n, p.nev, NB, K, s, Gm::SW);
   }
   const BatchModel model = batch_model(plans, NB, K, slots);
-  const bool one_launch =
-      opt.batch == ELPA_BATCH_ONE_LAUNCH ||
-      (opt.batch == ELPA_BATCH_AUTO && opt.steps <= 0 && model.seq <= 1.1 * model.diag);
-  std::vector<ProblemDesc> d(live.size());
-  size_t off = 0, tiles = 0, otiles = 0, ptiles = 0, units = 0;
-  int64_t T = 0;
-  std::vector<size_t> pat(d.size()), qat(d.size());
-  for (size_t i = 0; i < d.size(); ++i) {
+  B.one_launch = opt.batch == ELPA_BATCH_ONE_LAUNCH ||
+                 (opt.batch == ELPA_BATCH_AUTO && opt.steps <= 0 && model.seq <= 1.1 * model.diag);
+  B.d.resize(live.size());
+  B.pat.resize(live.size());
+  B.qat.resize(live.size());
+  B.rbytes.resize(live.size());
+  size_t off = 0;
+  for (size_t i = 0; i < B.d.size(); ++i) {
     const elpa_hh_problem& p = probs[live[i]];
     const DiagPlan& pl = plans[i];
-    ProblemDesc& x = d[i];
+    ProblemDesc& x = B.d[i];
     x.hh = p.hh;
     x.tau = p.tau;
     x.Q = p.Q;
@@ -707,90 +722,203 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
     x.S = (int)pl.S;
     x.rows_pad = pl.rows_pad;
     x.Jmax = (pl.n - 1 + NB - 1) / NB;
-    x.tile0 = (int)tiles;
-    x.otile0 = (int)otiles;
-    x.ptile0 = (int)ptiles;
-    x.unit0 = (int)units;
-    tiles += (size_t)(pl.rows_pad / 64 * x.GT);
-    otiles += (size_t)((pl.n + 63) / 64 * x.GT);
-    ptiles += (size_t)(pl.M * x.Jmax);
-    units += (size_t)pl.G;
-    pat[i] = off;
+    x.tile0 = (int)B.tiles;
+    x.otile0 = (int)B.otiles;
+    x.ptile0 = (int)B.ptiles;
+    x.unit0 = (int)B.units;
+    B.tiles += (size_t)(pl.rows_pad / 64 * x.GT);
+    B.otiles += (size_t)((pl.n + 63) / 64 * x.GT);
+    B.ptiles += (size_t)(pl.M * x.Jmax);
+    B.units += (size_t)pl.G;
+    B.pat[i] = off;
+    B.rbytes[i] = split_rbytes<E, NB, K>(pl.n);
     off += split_pbytes<E, NB, K>(pl.n);
-    qat[i] = off;
+    B.qat[i] = off;
     off += pl.template qbytes<E>();
-    T = std::max(T, pl.T);
+    B.T = std::max(B.T, pl.T);
   }
-  std::vector<DiagEntry> ent;
-  std::vector<int64_t> eoff((size_t)T + 1, 0), etiles((size_t)T, 0);
-  if (!one_launch) {
-    for (int64_t t = 0; t < T; ++t) {
-      eoff[(size_t)t] = (int64_t)ent.size();
+  B.eoff.assign((size_t)B.T + 1, 0);
+  B.etiles.assign((size_t)B.T, 0);
+  if (!B.one_launch) {
+    for (int64_t t = 0; t < B.T; ++t) {
+      B.eoff[(size_t)t] = (int64_t)B.ent.size();
       int64_t tl = 0;
-      for (size_t i = 0; i < d.size(); ++i) {
+      for (size_t i = 0; i < B.d.size(); ++i) {
         int64_t m0, c;
         plans[i].active(t, &m0, &c);
         if (c == 0) continue;
-        ent.push_back(DiagEntry{(int)i, (int)m0, (int)c, (int)tl});
+        B.ent.push_back(DiagEntry{(int)i, (int)m0, (int)c, (int)tl});
         tl += c * plans[i].G;
       }
-      etiles[(size_t)t] = tl;
+      B.etiles[(size_t)t] = tl;
     }
-    eoff[(size_t)T] = (int64_t)ent.size();
+    B.eoff[(size_t)B.T] = (int64_t)B.ent.size();
   }
-  if (tiles >= (size_t)INT32_MAX || otiles >= (size_t)INT32_MAX || ptiles >= (size_t)INT32_MAX ||
-      units >= (size_t)INT32_MAX)
+  if (B.tiles >= (size_t)INT32_MAX || B.otiles >= (size_t)INT32_MAX ||
+      B.ptiles >= (size_t)INT32_MAX || B.units >= (size_t)INT32_MAX)
     return hipErrorInvalidValue;
-  for (int64_t x : etiles)
+  for (int64_t x : B.etiles)
     if (x >= INT32_MAX) return hipErrorInvalidValue;
-  const size_t dbytes = align256(d.size() * sizeof(ProblemDesc));
-  const size_t ebytes = align256(std::max<size_t>(1, ent.size()) * sizeof(DiagEntry));
-  char* ws = nullptr;
-  hipError_t err = ws_alloc((void**)&ws, dbytes + ebytes + off, st);
-  if (err != hipSuccess) return err;
-  for (size_t i = 0; i < d.size(); ++i) {
-    d[i].P = ws + dbytes + ebytes + pat[i];
-    d[i].Bt = ws + dbytes + ebytes + pat[i] + split_rbytes<E, NB, K>(d[i].n);
-    d[i].Qs = ws + dbytes + ebytes + qat[i];
+  B.dbytes = align256(B.d.size() * sizeof(ProblemDesc));
+  B.ebytes = align256(std::max<size_t>(1, B.ent.size()) * sizeof(DiagEntry));
+  B.total = B.dbytes + B.ebytes + off;
+  return hipSuccess;
+}
+
+// Device addresses of the plan's areas in a workspace of B.total bytes.
+inline void bind_split_batch(SplitBatchPlan& B, char* ws) {
+  for (size_t i = 0; i < B.d.size(); ++i) {
+    B.d[i].P = ws + B.dbytes + B.ebytes + B.pat[i];
+    B.d[i].Bt = ws + B.dbytes + B.ebytes + B.pat[i] + B.rbytes[i];
+    B.d[i].Qs = ws + B.dbytes + B.ebytes + B.qat[i];
   }
-  int dev = 0;
-  (void)hipGetDevice(&dev);
-  PinnedStaging& stage = PinnedStaging::for_device(dev);
-  err = stage.upload(ws, d.data(), d.size() * sizeof(ProblemDesc), st);
-  if (err == hipSuccess && !ent.empty())
-    err = stage.upload(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry), st);
-  if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
-    return err;
-  }
+}
+
+// The launches of a bound plan whose descriptor and entry tables are in the
+// workspace: packing, layout conversion, the schedule, conversion back.
+template <typename E, int NB, int K, int OCC, int PD>
+void launch_split_batch(const SplitBatchPlan& B, const char* ws, int xcd, hipStream_t st) {
+  using Gm = SplitGeom<NB, K>;
   const ProblemDesc* dd = (const ProblemDesc*)ws;
-  const DiagEntry* de = (const DiagEntry*)(ws + dbytes);
-  const int count = (int)d.size();
-  hipLaunchKernelGGL((k_pack_split_b<E, NB, K>), dim3((unsigned)ptiles), dim3(256), 0, st, dd, count);
-  hipLaunchKernelGGL((k_to_rows_sw_b<E, Gm::SW>), dim3((unsigned)tiles), dim3(256), 0, st, dd, count);
+  const DiagEntry* de = (const DiagEntry*)(ws + B.dbytes);
+  const int count = (int)B.d.size();
+  hipLaunchKernelGGL((k_pack_split_b<E, NB, K>), dim3((unsigned)B.ptiles), dim3(256), 0, st, dd,
+                     count);
+  hipLaunchKernelGGL((k_to_rows_sw_b<E, Gm::SW>), dim3((unsigned)B.tiles), dim3(256), 0, st, dd,
+                     count);
   {
-    ProfScope prof(st, K, one_launch ? 0 : opt.steps);
-    if (one_launch) {
+    ProfScope prof(st, K, 0);
+    if (B.one_launch) {
       prof.before(st);
-      hipLaunchKernelGGL((k_split_seq<E, NB, K, OCC, PD>), dim3((unsigned)units), dim3(64), 0, st,
-                         dd, count);
+      hipLaunchKernelGGL((k_split_seq<E, NB, K, OCC, PD>), dim3((unsigned)B.units), dim3(64), 0,
+                         st, dd, count);
       prof.after(st);
     } else {
-      for (int64_t t = 0; t < T; ++t) {
-        const int64_t ne = eoff[(size_t)t + 1] - eoff[(size_t)t];
+      for (int64_t t = 0; t < B.T; ++t) {
+        const int64_t ne = B.eoff[(size_t)t + 1] - B.eoff[(size_t)t];
         if (ne == 0) continue;
         prof.before(st);
-        hipLaunchKernelGGL((k_split_b<E, NB, K, OCC, PD>), dim3((unsigned)etiles[(size_t)t]),
-                           dim3(64), 0, st, dd, de + eoff[(size_t)t], (int)ne, (int)t, opt.xcd);
+        hipLaunchKernelGGL((k_split_b<E, NB, K, OCC, PD>), dim3((unsigned)B.etiles[(size_t)t]),
+                           dim3(64), 0, st, dd, de + B.eoff[(size_t)t], (int)ne, (int)t, xcd);
         prof.after(st);
       }
     }
   }
-  hipLaunchKernelGGL((k_from_rows_sw_b<E, Gm::SW>), dim3((unsigned)otiles), dim3(256), 0, st, dd,
-                     count);
+  hipLaunchKernelGGL((k_from_rows_sw_b<E, Gm::SW>), dim3((unsigned)B.otiles), dim3(256), 0, st,
+                     dd, count);
+}
+
+// Batched call: plan, stream-ordered workspace, tables staged through pinned
+// host memory, launches, workspace freed in stream order.
+template <typename E, int NB, int K, int OCC, int PD>
+hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
+                                TileOpts opt, hipStream_t st, int num_cu) {
+  SplitBatchPlan B;
+  hipError_t err = plan_split_batch<E, NB, K, OCC, PD>(probs, idx, cnt, opt, num_cu, &B);
+  if (err != hipSuccess || B.d.empty()) return err;
+  char* ws = nullptr;
+  err = ws_alloc((void**)&ws, B.total, st);
+  if (err != hipSuccess) return err;
+  bind_split_batch(B, ws);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  PinnedStaging& stage = PinnedStaging::for_device(dev);
+  err = stage.upload(ws, B.d.data(), B.d.size() * sizeof(ProblemDesc), st);
+  if (err == hipSuccess && !B.ent.empty())
+    err = stage.upload(ws + B.dbytes, B.ent.data(), B.ent.size() * sizeof(DiagEntry), st);
+  if (err != hipSuccess) {
+    (void)hipFreeAsync(ws, st);
+    return err;
+  }
+  launch_split_batch<E, NB, K, OCC, PD>(B, ws, opt.xcd, st);
   err = hipGetLastError();
   const hipError_t e2 = hipFreeAsync(ws, st);
   return err != hipSuccess ? err : e2;
+}
+
+// Prepared group (elpa_hh_batch_create): the workspace and tables live on the
+// device for the handle's lifetime; run() only launches.  A single problem
+// runs the single-call path (stripe groups on library streams) on the owned
+// workspace; several run the batched schedule.
+template <typename E, int NB, int K, int OCC, int PD>
+class SplitPrepared : public PreparedGroup {
+ public:
+  ~SplitPrepared() override {
+    if (ws_) (void)hipFree(ws_);
+  }
+  hipError_t init(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt, TileOpts opt,
+                  int num_cu) {
+    opt_ = opt;
+    num_cu_ = num_cu;
+    int live = 0;
+    for (int64_t i = 0; i < cnt; ++i)
+      if (probs[idx[i]].n > 1 && probs[idx[i]].nev > 0) {
+        ++live;
+        single_ = probs[idx[i]];
+      }
+    if (live == 0) return hipSuccess;
+    if (live == 1) {
+      one_ = true;
+      bytes_ = split_workspace<E, NB, K>(single_.n, single_.nev);
+      return alloc(bytes_);
+    }
+    hipError_t err = plan_split_batch<E, NB, K, OCC, PD>(probs, idx, cnt, opt, num_cu, &B_);
+    if (err != hipSuccess) return err;
+    bytes_ = B_.total;
+    err = alloc(bytes_);
+    if (err != hipSuccess) return err;
+    bind_split_batch(B_, (char*)ws_);
+    err = hipMemcpy(ws_, B_.d.data(), B_.d.size() * sizeof(ProblemDesc), hipMemcpyHostToDevice);
+    if (err == hipSuccess && !B_.ent.empty())
+      err = hipMemcpy((char*)ws_ + B_.dbytes, B_.ent.data(), B_.ent.size() * sizeof(DiagEntry),
+                      hipMemcpyHostToDevice);
+    return err;
+  }
+  hipError_t run(hipStream_t st) override {
+    if (!ws_) return hipSuccess;
+    if (one_)
+      return run_split<E, NB, K, OCC, PD>(single_.hh, single_.tau, single_.Q, single_.ldq,
+                                          single_.n, single_.nev, opt_, st, num_cu_, ws_);
+    launch_split_batch<E, NB, K, OCC, PD>(B_, (const char*)ws_, opt_.xcd, st);
+    return hipGetLastError();
+  }
+  size_t bytes() const override { return bytes_; }
+
+ private:
+  hipError_t alloc(size_t b) {
+    size_t tot = 0;
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess && hipDeviceTotalMem(&tot, dev) == hipSuccess &&
+        tot && b > tot)
+      return hipErrorOutOfMemory;
+    const hipError_t e = hipMalloc(&ws_, b);
+    if (e != hipSuccess) {
+      ws_ = nullptr;
+      (void)hipGetLastError();
+    }
+    return e;
+  }
+  SplitBatchPlan B_;
+  elpa_hh_problem single_{};
+  bool one_ = false;
+  TileOpts opt_{};
+  int num_cu_ = 0;
+  void* ws_ = nullptr;
+  size_t bytes_ = 0;
+};
+
+template <typename E, int NB, int K, int OCC, int PD>
+hipError_t prepare_split(const elpa_hh_problem* probs, const int64_t* idx, int64_t cnt,
+                         TileOpts opt, int num_cu, PreparedGroup** out) {
+  auto* g = new SplitPrepared<E, NB, K, OCC, PD>();
+  const hipError_t err = g->init(probs, idx, cnt, opt, num_cu);
+  if (err != hipSuccess) {
+    delete g;
+    *out = nullptr;
+    return err;
+  }
+  *out = g;
+  return hipSuccess;
 }
 
 }  // namespace ehh

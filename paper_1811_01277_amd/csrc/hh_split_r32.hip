@@ -7,7 +7,7 @@ namespace ehh {
 #define EHH_SPLIT(E, DT, NB, K, OCC, PD)                                               \
   {ELPA_PATH_SPLIT, DT, NB, K, OCC, &launch_split<E, NB, K, OCC, PD>,              \
    &launch_split_batched<E, NB, K, OCC, PD>, &split_workspace<E, NB, K>,           \
-   &launch_split_ws<E, NB, K, OCC, PD>}
+   &launch_split_ws<E, NB, K, OCC, PD>, &prepare_split<E, NB, K, OCC, PD>}
 
 const StripeEntry* split_table_r32(int* size) {
   static const StripeEntry table[] = {

@@ -24,12 +24,19 @@ computation runs in the HIP library):
   stripe-group streams (each slot stream forks onto library streams of its
   own); larger batches run as one elpa_hh_trafo_batched call;
 * completion is tracked with events; a solve that depends on an earlier one
-  (the next step of the same SCF sequence) becomes ready when that completes.
+  (the next step of the same SCF sequence) becomes ready when that completes;
+* graphs (optional): an SCF sequence repeats the same call on the same
+  buffers, so prepare_graphs() builds, per sequence buffer set, a prepared
+  batch (elpa_hh_batch_create: workspace and tables resident like the
+  sequence's Q and reflectors) and captures its run into a HIP graph; a
+  request that runs alone then replays that graph on its slot stream instead
+  of issuing the call's launches one by one.
 
-Times: arrivals and readiness on the host clock of the trace; completion is
-the device time of an event recorded behind the request's work, placed on the
-same clock through an event recorded at the trace start (so the poll loop's
-granularity does not bias it).  Latency of a request = completion -
+Times: arrivals and readiness on the host clock of the trace; start and
+completion are the device times of events recorded before and behind the
+request's work, placed on the same clock through an event recorded at the
+trace start (so the poll loop's granularity does not bias them; the two time
+bases agree to the event timestamps' resolution, a few microseconds).  Latency of a request = completion -
 max(arrival, completion of the solve it depends on).  `run_plain` serves the
 same requests one call at a time on one stream, as the baseline, timed the
 same way.
@@ -98,12 +105,19 @@ class _Clock:
         return min(self.e0.elapsed_time(ev) * 1e-3, self.now())
 
 
+def _key(r):
+    return (r.q.data_ptr(), r.hh.data_ptr(), r.tau.data_ptr(), tuple(r.q.shape),
+            tuple(r.q.stride()), str(r.q.dtype), r.nbw)
+
+
 class Server:
     def __init__(self, device, slots=3, budget_bytes=None, max_batch=32, poll_s=50e-6):
         import torch
         self.torch = torch
         self.device = device
         self.streams = [torch.cuda.Stream(device=device) for _ in range(slots)]
+        self.graphs = {}        # buffer set -> (prepared batch, captured graph)
+        self.replays = 0
         if budget_bytes is None:
             free, _ = torch.cuda.mem_get_info(device)
             budget_bytes = int(0.5 * free)
@@ -114,6 +128,30 @@ class Server:
         self.max_in_use = 0     # peak admitted workspace bytes
         self.max_busy = 0       # peak number of slots running at once
 
+    def prepare_graphs(self, requests):
+        """Prepared batch and captured graph for every distinct buffer set of
+        the requests (setup, outside the timed service).  Returns the device
+        bytes the prepared batches hold."""
+        torch = self.torch
+        cap = torch.cuda.Stream(device=self.device)
+        for r in requests:
+            k = _key(r)
+            if k in self.graphs:
+                continue
+            b = B.Batch([(r.q, r.hh, r.tau, r.nbw)])
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=cap):
+                b.run(cap)
+            self.graphs[k] = (b, g)
+        torch.cuda.synchronize(self.device)
+        return sum(b.nbytes for b, _ in self.graphs.values())
+
+    def close_graphs(self):
+        self.torch.cuda.synchronize(self.device)
+        for b, _ in self.graphs.values():
+            b.close()
+        self.graphs = {}
+
     def run(self, requests):
         """Replay the requests' arrival times against the wall clock; returns
         when all are done.  Requests are updated in place with their times."""
@@ -121,7 +159,7 @@ class Server:
         pending = sorted(requests, key=lambda r: r.arrival)
         done_at = {}
         waiting, ready = [], []
-        busy = [None] * len(self.streams)  # (event, batch, bytes)
+        busy = [None] * len(self.streams)  # (done event, batch, bytes, start event)
         in_use = 0
         left = len(pending)
         pi = 0
@@ -132,7 +170,9 @@ class Server:
             for i, b in enumerate(busy):
                 if b is not None and b[0].query():
                     t = clock.at(b[0])
+                    t_s = clock.at(b[3])
                     for r in b[1]:
+                        r.t_start = t_s
                         r.t_done = t
                         done_at[r.rid] = t
                     in_use -= b[2]
@@ -160,6 +200,8 @@ class Server:
                 cap = min(self.max_batch, -(-len(ready) // free))
                 batch, nbytes, rest = [], 0, []
                 for r in ready:
+                    # (conservative for a request that replays its graph, whose
+                    # workspace is resident: it may still join a batched call)
                     f = footprint(r)
                     fits = in_use + nbytes + f <= self.budget
                     # an idle device always takes the oldest request
@@ -172,16 +214,20 @@ class Server:
                     break
                 ready = rest
                 st = self.streams[i]
-                if len(batch) == 1:
+                ev0 = torch.cuda.Event(enable_timing=True)
+                ev0.record(st)
+                if len(batch) == 1 and _key(batch[0]) in self.graphs:
+                    with torch.cuda.stream(st):
+                        self.graphs[_key(batch[0])][1].replay()
+                    self.replays += 1
+                elif len(batch) == 1:
                     r = batch[0]
                     B.hh_trafo(r.q, r.hh, r.tau, r.nbw, stream=st)  # library plan
                 else:
                     B.hh_trafo_batched([(r.q, r.hh, r.tau, r.nbw) for r in batch], stream=st)
                 ev = torch.cuda.Event(enable_timing=True)
                 ev.record(st)
-                for r in batch:
-                    r.t_start = now
-                busy[i] = (ev, batch, nbytes)
+                busy[i] = (ev, batch, nbytes, ev0)
                 in_use += nbytes
                 self.batches.append((i, len(batch), nbytes))
                 self.max_in_use = max(self.max_in_use, in_use)
@@ -214,11 +260,13 @@ def run_plain(requests, device, poll_s=50e-6):
             continue
         queue.remove(r)
         r.t_ready = max(r.arrival, done_at.get(r.after, 0.0))
-        r.t_start = now
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev0.record(st)
         B.hh_trafo(r.q, r.hh, r.tau, r.nbw, stream=st)
         ev = torch.cuda.Event(enable_timing=True)
         ev.record(st)
         ev.synchronize()
+        r.t_start = clock.at(ev0)
         r.t_done = clock.at(ev)
         done_at[r.rid] = r.t_done
     return requests
