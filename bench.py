@@ -800,7 +800,12 @@ def main():
     in_flight = prof["sum_launch_ms"] / prof["kernel_ms"]
     achieved = (flops / launches) / (avg_launch_ms * 1e-3) * in_flight / 1e12
     peak = PEAK_TFLOPS[dt]
-    kname = {1: "k_ref", 2: "k_diag", 3: "k_split"}.get(prof["path"], "?")
+    kname = {1: "k_ref", 2: "k_diag", 3: "k_split", 4: "k_wy"}.get(prof["path"], "?")
+    # the compact-WY kernel runs on the matrix cores and executes (nbw+16)/nbw
+    # times the counted flops (its sub-groups' parallelograms padded to whole
+    # 16-row tiles); the VALU kernels execute the counted flops
+    mfma = prof["path"] == 4
+    executed = achieved * ((nbw + 16) / nbw if mfma else 1.0)
     traffic = recorded_traffic({"n": n, "nbw": nbw, "nev": nev, "dtype": dt, "path": prof["path"],
                                 "k": prof["k"], "tile_steps": prof["steps"],
                                 "streams": prof["streams"]})
@@ -818,7 +823,9 @@ def main():
         # dominant kernel's own rate is roofline.achieved
         "pct_peak_whole_call": round(100.0 * value / 1e3 / peak, 2),
         "peak_tflops": peak,
-        "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": peak,
+        "roofline": {"bound": "mfma" if mfma else "alu", "achieved": round(achieved, 3),
+                     "peak": peak, "achieved_executed": round(executed, 3),
+                     "frac_executed": round(executed / peak, 4),
                      "unit": "TFLOP/s", "frac": round(achieved / peak, 4),
                      "traffic": None if traffic is None else round(traffic),
                      "kernel": kname, "launches": prof["launches"],

@@ -40,7 +40,9 @@ const ehh::StripeEntry* find_entry(int path, int32_t dtype, int64_t nb, int k) {
 // compiled entry in order of preference (0 if none).
 int default_k(int path, int32_t dtype, int64_t nb) {
   static const int split_pref[] = {80, 64, 48, 32, 96, 24, 16};
-  static const int wy_pref[] = {64, 48, 32, 96};
+  static const int wy_pref[] = {160, 128, 96, 64, 48, 32};
+  static const int wy_pref32[] = {96, 64, 32, 128};
+  static const int wy_pref_c[] = {48, 32, 16};
   static const int stripe_pref[] = {32, 16, 8, 4};
   static const int stripe_pref_c[] = {4, 2};
   if (path == ELPA_PATH_SPLIT) {
@@ -49,8 +51,10 @@ int default_k(int path, int32_t dtype, int64_t nb) {
     return 0;
   }
   if (path == ELPA_PATH_WY) {
-    for (int k : wy_pref)
-      if (find_entry(path, dtype, nb, k)) return k;
+    const int* pref = dtype == ELPA_C64 ? wy_pref_c : dtype == ELPA_R32 ? wy_pref32 : wy_pref;
+    const int cnt = dtype == ELPA_C64 ? 3 : dtype == ELPA_R32 ? 4 : 6;
+    for (int i = 0; i < cnt; ++i)
+      if (find_entry(path, dtype, nb, pref[i])) return pref[i];
     return 0;
   }
   if (dtype == ELPA_C64) {
@@ -63,12 +67,28 @@ int default_k(int path, int32_t dtype, int64_t nb) {
   return 0;
 }
 
-// Kernel that runs (dtype, nb) under `plan` (NULL = library choice).  Returns
-// the table entry, or nullptr with *path = ELPA_PATH_REF for the reference
-// kernel; *rc = ELPA_ERR_PLAN if an explicit plan cannot run.  batched: the
-// kernel must have a batched form (the library choice skips those without).
+// Library choice for a single problem of size n with semi-bandwidth 64, from
+// sweeps over n = 1000 .. 20000 (nev = n) on this GPU: the compact-WY MFMA
+// kernel for fp32 (k = 96) and complex fp64 (k = 48) at every size, and for
+// fp64 from n = 3000 on (k = 128, from n = 6000 k = 160: a larger k reuses
+// every loaded row more but leaves fewer sweep blocks to run side by side);
+// 0 = the two-lane VALU kernel (fp64 below n = 3000, other nbw, batched
+// calls).
+int auto_wy_k(int32_t dtype, int64_t nb, int64_t n) {
+  if (nb != 64) return 0;
+  if (dtype == ELPA_R32) return 96;
+  if (dtype == ELPA_C64) return 48;
+  if (dtype == ELPA_R64 && n >= 3000) return n >= 6000 ? 160 : 128;
+  return 0;
+}
+
+// Kernel that runs (dtype, nb) of size n under `plan` (NULL = library
+// choice).  Returns the table entry, or nullptr with *path = ELPA_PATH_REF for
+// the reference kernel; *rc = ELPA_ERR_PLAN if an explicit plan cannot run.
+// batched: the kernel must have a batched form, and the library choice
+// prefers the two-lane kernel (its one-launch batched schedule).
 const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* plan, int* path,
-                                int* rc, bool batched = false) {
+                                int* rc, bool batched = false, int64_t n = 0) {
   *rc = ELPA_OK;
   if (plan && (plan->order < ELPA_ORDER_AUTO || plan->order > ELPA_ORDER_XCD ||
                plan->streams < 0 || plan->streams > 8 || plan->batch < ELPA_BATCH_AUTO ||
@@ -94,6 +114,14 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
       return e;
     }
     case ELPA_PATH_AUTO: {
+      if (!batched && k == 0) {
+        const int wk = auto_wy_k(dtype, nb, n);
+        const ehh::StripeEntry* e = wk ? find_entry(ELPA_PATH_WY, dtype, nb, wk) : nullptr;
+        if (e) {
+          *path = ELPA_PATH_WY;
+          return e;
+        }
+      }
       // the two-lane VALU kernel where one is compiled (fp64, fp32 and
       // complex), then for fp32 the compact-WY MFMA path, then the one-lane
       // kernel
@@ -235,7 +263,7 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
   elpa_hh_plan tuned{};
   plan = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0;
-  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc);
+  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc, false, n);
   if (rc != ELPA_OK) return rc;
   if (n <= 1 || nev == 0) return ELPA_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -441,7 +469,7 @@ int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dty
   elpa_hh_plan tuned{};
   plan = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0, rc = 0;
-  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc);
+  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc, false, n);
   if (rc != ELPA_OK) return -1;
   if (n <= 1 || nev == 0 || !se) return 0;
   return (int64_t)se->workspace(n, nev);

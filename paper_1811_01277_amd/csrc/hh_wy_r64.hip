@@ -1,0 +1,26 @@
+// Compact-WY MFMA kernel instances for real fp64 (one translation unit per
+// element type, so that the variants compile in parallel).
+#include "hh_wy_impl.h"
+
+namespace ehh {
+
+#define EHH_WY(E, DT, NB, K, T, OCC, PF, VP)                                             \
+  {ELPA_PATH_WY, DT, NB, K, OCC, &launch_wy<E, NB, K, T, OCC, PF, VP>,                 \
+   &launch_wy_batched<E, NB, K, T, OCC, PF, VP>, &wy_workspace<E, NB, K, T>, nullptr, nullptr}
+
+const StripeEntry* wy_table_r64(int* size) {
+  static const StripeEntry table[] = {
+      // (dtype, nbw, k, column tiles per wave, waves per SIMD, next rows
+      // prefetched, V fragments prefetched)
+      EHH_WY(double, 0, 64, 64, 2, 1, true, true), EHH_WY(double, 0, 64, 96, 2, 1, true, false),
+      EHH_WY(double, 0, 64, 128, 2, 1, true, false), EHH_WY(double, 0, 64, 112, 2, 1, false, false),
+      EHH_WY(double, 0, 64, 160, 2, 1, false, false), EHH_WY(double, 0, 64, 144, 2, 1, false, false),
+      EHH_WY(double, 0, 64, 48, 2, 1, true, true), EHH_WY(double, 0, 64, 32, 2, 1, true, true),
+      EHH_WY(double, 0, 32, 64, 2, 1, true, true), EHH_WY(double, 0, 32, 96, 2, 1, true, true),
+      EHH_WY(double, 0, 32, 32, 2, 1, true, true),
+  };
+  *size = (int)(sizeof(table) / sizeof(table[0]));
+  return table;
+}
+
+}  // namespace ehh

@@ -127,11 +127,14 @@ def test_plan_support_table():
     assert not P.plan_supported(64, P.R64, P.PATH_SPLIT, 63)
     assert not P.plan_supported(16, P.R64, P.PATH_SPLIT)
     assert not P.plan_supported(64, P.R64, 5)                # no such path
-    # compact-WY MFMA path: real fp64 / fp32, nbw 32 / 64, k a multiple of 16
-    for nbw, k, dt in [(64, 32, P.R64), (64, 64, P.R64), (32, 96, P.R64), (64, 64, P.R32)]:
+    # compact-WY MFMA path: real fp64 / fp32 and complex fp64, nbw 32 / 64, k a
+    # multiple of 16
+    for nbw, k, dt in [(64, 32, P.R64), (64, 64, P.R64), (32, 64, P.R64), (64, 64, P.R32),
+                       (64, 32, P.C64), (64, 16, P.C64), (32, 32, P.C64)]:
         assert P.plan_supported(nbw, dt, P.PATH_WY, k), (nbw, k, dt)
-    assert not P.plan_supported(64, P.C64, P.PATH_WY)
+    assert P.plan_supported(64, P.C64, P.PATH_WY)            # library default k
     assert not P.plan_supported(64, P.R64, P.PATH_WY, 40)
+    assert not P.plan_supported(64, P.C64, P.PATH_WY, 64)
     rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 3)   # unknown order
     assert rc == -6
     rc = P.hh_trafo_ptr(10, 5, 2, 8, 8, 8, 10, P.R64, 0, None, 0, 0, 0, 9)  # > 8 streams
@@ -149,6 +152,32 @@ def split_ws_brute(n, nev, nbw, k, es):
     steps = sum(-(-(n - 1 - m * k) // nbw) for m in range(M))
     rs = 2 * (nbw // 2 + 2)
     return al((steps * k * rs + 32) * es) + al(M * 8) + al(rows_pad * (-(-nev // 32)) * 32 * es)
+
+
+def wy_ws_brute(n, nev, nbw, k, es, planes, tiles):
+    """Workspace of the compact-WY kernel by direct summation: per sweep block
+    and existing chase step, k/16 sub-group records of 2 x planes x 4 (nbw/16+1)
+    fragments of 64 values; the block table; the stripe copy of Q in stripes of
+    16 x tiles columns."""
+    al = lambda x: -(-x // 256) * 256
+    rows_pad = -(-(n + nbw + k) // 64) * 64
+    M = -(-(n - 1) // k)
+    steps = sum(-(-(n - 1 - m * k) // nbw) for m in range(M))
+    rec = 2 * planes * 4 * (nbw // 16 + 1) * 64
+    sw = 16 * tiles
+    return (al(steps * (k // 16) * rec * es) + al(M * 8) +
+            al(rows_pad * (-(-nev // sw)) * sw * es * (2 if planes == 2 else 1)))
+
+
+@pytest.mark.parametrize("dt,nbw,k,planes,tiles", [("r64", 64, 160, 1, 2), ("r64", 64, 64, 1, 2),
+                                                  ("r64", 32, 96, 1, 2), ("r32", 64, 96, 1, 2),
+                                                  ("c64", 64, 48, 2, 1)])
+def test_wy_workspace_matches_direct_sum(dt, nbw, k, planes, tiles):
+    code = {"r64": P.R64, "r32": P.R32, "c64": P.C64}[dt]
+    es = {"r64": 8, "r32": 4, "c64": 8}[dt]
+    for n in list(range(2, 300, 7)) + [1000, 4097, 20000]:
+        assert P.workspace_bytes(n, 70, nbw, code, P.PATH_WY, k) == \
+            wy_ws_brute(n, 70, nbw, k, es, planes, tiles), n
 
 
 @pytest.mark.parametrize("nbw,k", [(64, 48), (64, 64), (64, 80), (32, 32), (32, 64), (32, 96)])
@@ -174,7 +203,9 @@ def test_workspace_bytes():
     n, nev, nbw, k = 20000, 20000, 64, 80
     want = split_ws_brute(n, nev, nbw, k, 8)
     assert P.workspace_bytes(n, nev, nbw, P.R64, P.PATH_SPLIT, k) == want
-    assert P.workspace_bytes(n, nev, nbw, P.R64) == want        # the library default
+    # the library default at this size: the compact-WY kernel, k = 160
+    assert P.workspace_bytes(n, nev, nbw, P.R64) == wy_ws_brute(n, nev, nbw, 160, 8, 1, 2)
+    assert P.workspace_bytes(2000, 2000, nbw, P.R64) == split_ws_brute(2000, 2000, nbw, 80, 8)
     assert P.workspace_bytes(n, nev, nbw, P.C64) > 0
     # batched: the kernels a batched call picks, plus descriptor tables
     one = P.workspace_bytes_batched([(n, nev, nbw, P.R64)])

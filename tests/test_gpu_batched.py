@@ -66,7 +66,7 @@ def test_batch_matches_oracle_and_single_calls(torch_dev, sched):
     for (q, h, t, nbw) in probs:
         qq = q.clone()  # new storage, same column-major strides
         assert qq.data_ptr() != q.data_ptr() and qq.stride() == q.stride()
-        P.hh_trafo(qq, h, t, nbw)
+        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT)   # the kernel batched calls run
         singles.append(qq)
     print("batch of", len(probs), "problems", flush=True)
     P.profile_enable(True)
@@ -96,7 +96,7 @@ def test_fp32_batch_equals_single_calls(torch_dev, family):
     oracle."""
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
-    path = P.PATH_WY if family == "wy" else None
+    path = P.PATH_WY if family == "wy" else P.PATH_SPLIT
     sizes = [(300, 64, 150), (517, 64, 517), (130, 32, 33), (260, 64, 97)]
     probs, host = [], []
     for i, (n, nbw, nev) in enumerate(sizes):
@@ -180,7 +180,7 @@ def test_batched_workload_sampled(torch_dev):
     for i in check:
         q, h, t, nbw = probs[i]
         qq = q.clone()
-        P.hh_trafo(qq, h, t, nbw)
+        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT)
         singles[i] = qq
     print("batched workload: 256 problems", flush=True)
     P.profile_enable(True)
@@ -219,7 +219,7 @@ def test_one_launch_batch_other_dtypes(torch_dev, dt):
     singles = []
     for (q, h, t, nbw) in probs:
         qq = q.clone()
-        P.hh_trafo(qq, h, t, nbw)
+        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT)
         singles.append(qq)
     P.profile_enable(True)
     try:

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
 KS = [1, 2, 4, 6, 8, 16, 24, 32, 40, 48, 64]
 SPLIT_KS = [16, 24, 32, 48, 64, 80, 96, 128]
-WY_KS = [32, 48, 64, 96]
+WY_KS = [16, 32, 48, 64, 96, 112, 128, 144, 160]
 
 
 @pytest.fixture(scope="module")
@@ -332,6 +332,7 @@ FULL = [
     (20000, 64, 2000, "r64", (2, 32)),   # one-lane stripe kernel at full size
     (20000, 64, 2000, "r64", (4, 64)),   # compact-WY MFMA path
     (20000, 64, 2000, "r32", (4, 64)),
+    (20000, 64, 2000, "c64", (4, 32)),   # compact-WY MFMA path, complex (planar)
     (20000, 64, 2000, "c64", (2, 4)),    # one-lane stripe kernel, complex
     (20000, 64, 2000, "r32", None), (20000, 64, 2000, "c64", None),
 ]

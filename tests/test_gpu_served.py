@@ -199,7 +199,9 @@ def test_served_with_graphs_equals_alone(torch_dev):
     assert srv.replays > 0 and held > 0
     for i, r in enumerate(reqs):
         q = inputs[i].t().contiguous().t()
-        P.hh_trafo(q, r.hh, r.tau, r.nbw)
+        # graphs and batches run the two-lane kernel; the bitwise comparison is
+        # with that kernel alone
+        P.hh_trafo(q, r.hh, r.tau, r.nbw, path=P.PATH_SPLIT)
         torch.cuda.synchronize()
         assert torch.equal(q, r.q), i
     srv.close_graphs()

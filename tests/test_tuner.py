@@ -34,7 +34,7 @@ def test_set_refuses_plans_that_cannot_run():
         P.tuner_set(P.R64, 64, 1000, 1000, path=P.PATH_SPLIT, k=63)
     assert e.value.code == -6
     with pytest.raises(P.ElpaError) as e:
-        P.tuner_set(P.C64, 64, 1000, 1000, path=P.PATH_WY)
+        P.tuner_set(P.C64, 64, 1000, 1000, path=P.PATH_WY, k=64)   # no such complex WY k
     assert e.value.code == -6
     with pytest.raises(P.ElpaError) as e:
         P.tuner_set(P.R64, 64, 1000, 1000, path=P.PATH_SPLIT, k=64, streams=9)
