@@ -75,6 +75,9 @@ def parse():
                          "0.8x and 1.25x the plain path's measured capacity)")
     ap.add_argument("--served-only", action="store_true",
                     help="instead of the benchmark: only the served stream leg")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="instead of the benchmark: measured fp64 / fp32 FMA and MFMA issue rates "
+                         "(elpa_peak_probe) at 1, 2 and 4 waves per SIMD")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="instead of the benchmark: copy a MIB-MiB device buffer 3 times "
                          "(reference kernel of known size for the HBM byte counters)")
@@ -645,6 +648,32 @@ def copy_calibration(mib):
           flush=True)
 
 
+def peak_probe():
+    """Measured issue rates of the arithmetic units (include/elpa_probe.h)."""
+    import ctypes as C
+    import torch
+    import paper_1811_01277_amd as P
+    torch.cuda.init()
+    L = P.library()
+    L.elpa_peak_probe.argtypes = [C.c_int32, C.c_int32, C.c_int64, C.POINTER(C.c_double),
+                                  C.POINTER(C.c_double)]
+    L.elpa_peak_probe.restype = C.c_int
+    names = {0: "fp64 vector FMA", 1: "fp64 MFMA 16x16x4", 2: "fp32 MFMA 16x16x4",
+             3: "fp32 vector FMA (no packed)"}
+    iters = {0: 800000, 1: 40000, 2: 80000, 3: 800000}
+    vendor = {0: 78.6, 1: 78.6, 2: 157.3, 3: 78.6}
+    rows = []
+    for kind in range(4):
+        for w in (1, 2, 4):
+            tf, ms = C.c_double(), C.c_double()
+            rc = L.elpa_peak_probe(kind, w, iters[kind], C.byref(tf), C.byref(ms))
+            if rc != 0:
+                raise RuntimeError(P.strerror(rc))
+            rows.append({"unit": names[kind], "waves_per_simd": w, "tflops": round(tf.value, 2),
+                         "ms": round(ms.value, 2), "vendor_peak_tflops": vendor[kind]})
+    print(json.dumps({"peak_probe": rows}), flush=True)
+
+
 def counted_flops(n, nev, dt):
     return (8 if dt == "c64" else 2) * n * (n - 1) * nev
 
@@ -732,6 +761,9 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.peak_probe:
+        peak_probe()
         return
     if args.solve_only:
         print(json.dumps({"solve": solve_leg(args)}), flush=True)

@@ -18,7 +18,7 @@ SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_stripe_r64.hip",
            "hh_stripe_r32.hip", "hh_stripe_c64.hip", "hh_split.hip", "hh_split_r64.hip",
            "hh_split_r32.hip", "hh_split_c64.hip", "hh_wy.hip", "hh_wy_r64.hip",
            "hh_wy_r32.hip", "hh_wy_c64.hip", "bt2.hip", "b2t.hip", "f2b.hip",
-           "gen.hip", "dc.hip", "hh_noalloc.hip"]
+           "gen.hip", "dc.hip", "hh_noalloc.hip", "peak_probe.hip"]
 ARCH = os.environ.get("ELPA_HIP_ARCH", "gfx950")
 
 FLAGS = [
