@@ -41,6 +41,8 @@ def parse():
     ap.add_argument("--k", type=int, default=0, help="sweeps fused per pass (0 = auto)")
     ap.add_argument("--tile-steps", type=int, default=0,
                     help="chase steps per tile of the launch schedule (0 = auto)")
+    ap.add_argument("--order", type=int, default=0,
+                    help="tile order over workgroup ids: 0 auto, 1 linear, 2 per-XCD runs")
     ap.add_argument("--streams", type=int, default=0,
                     help="stripe groups on concurrent streams (0 = auto)")
     ap.add_argument("--seed", type=int, default=301)
@@ -801,7 +803,8 @@ def main():
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream(dev)
 
-    plan = dict(path=args.path, k=args.k, steps=args.tile_steps, streams=args.streams)
+    plan = dict(path=args.path, k=args.k, steps=args.tile_steps, streams=args.streams,
+                order=args.order)
     for _ in range(args.warmup):
         P.hh_trafo(q, h, t, nbw, stream=stream, **plan)
     torch.cuda.synchronize()
