@@ -75,6 +75,10 @@ def parse():
     ap.add_argument("--served-rates", default="",
                     help="Poisson arrival rates of the served stream (requests / s; default "
                          "0.8x and 1.25x the plain path's measured capacity)")
+    ap.add_argument("--batch-flops", type=float, default=5e10,
+                    help="served stream: work bound of a batch (counted flops)")
+    ap.add_argument("--call-streams", type=int, default=1,
+                    help="served stream: stripe-group streams per call (0: library choice)")
     ap.add_argument("--served-only", action="store_true",
                     help="instead of the benchmark: only the served stream leg")
     ap.add_argument("--peak-probe", action="store_true",
@@ -113,6 +117,7 @@ def served_stream(args):
     import paper_1811_01277_amd as P
     dev = torch.device("cuda:0")
     nseq, steps, switch = 64, 20, 5
+    bf, cs = args.batch_flops, args.call_streams
     sizes = W.scf_sequence_sizes(nseq, 1000, 6000, seed=501)
     g = torch.Generator(device=dev)
     g.manual_seed(510000)
@@ -138,22 +143,22 @@ def served_stream(args):
     warm = requests(1000.0)[:nseq]    # one solve per sequence, untimed
     for r in warm:
         r.arrival, r.after = 0.0, -1
-    Server(dev, slots=3, max_batch=32).run(warm)
+    Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs).run(warm)
     cap = latency_stats(run_plain(requests(1e9), dev))["solves_per_s"]
     if args.served_rates:
         rates = [float(x) for x in args.served_rates.split(",") if x]
     else:
         rates = [round(0.8 * cap, 1), round(1.25 * cap, 1)]
     # per-sequence graphs of prepared batches (setup, not timed)
-    gsrv = Server(dev, slots=3, max_batch=32)
+    gsrv = Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs)
     t0 = time.perf_counter()
     gbytes = gsrv.prepare_graphs(requests(1e9))
     gsetup = time.perf_counter() - t0
     runs = []
     for rate in rates:
-        srv = Server(dev, slots=3, max_batch=32)
+        srv = Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs)
         served = latency_stats(srv.run(requests(rate)))
-        gsrv.batches, gsrv.replays = [], 0
+        gsrv.batches, gsrv.replays, gsrv.launch_s = [], 0, 0.0
         with_graphs = latency_stats(gsrv.run(requests(rate)))
         plain = latency_stats(run_plain(requests(rate), dev))
         runs.append({"rate_per_s": rate, "rate_vs_plain_capacity": round(rate / cap, 3),
@@ -164,7 +169,9 @@ def served_stream(args):
                      "graphs_solves_per_s_vs_plain": round(with_graphs["solves_per_s"] /
                                                            plain["solves_per_s"], 3),
                      "graphs_p99_vs_plain": round(with_graphs["p99_ms"] / plain["p99_ms"], 3),
-                     "batches": len(srv.batches), "graph_replays": gsrv.replays})
+                     "batches": len(srv.batches), "graph_replays": gsrv.replays,
+                     "host_launch_s": round(srv.launch_s, 3),
+                     "graphs_host_launch_s": round(gsrv.launch_s, 3)})
     gsrv.close_graphs()
     # precision switching at 0.8x capacity; sampled sequences' fp64 buffers
     # checked against the oracle after the served run (each holds its input
@@ -174,20 +181,20 @@ def served_stream(args):
     cols = [0, 1]
     before = {q: state[q]["r64"][0][:, cols].cpu().numpy() for q in sample}
     sw_reqs = requests(rate, switch_step=switch)
-    Server(dev, slots=3, max_batch=32).run(sw_reqs)
+    Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs).run(sw_reqs)
     sw_served = latency_stats(sw_reqs)
     after = {q: state[q]["r64"][0][:, cols].cpu().numpy() for q in sample}
     n64 = {q: sum(1 for r in sw_reqs if r.seq == q and r.q.dtype == torch.float64)
            for q in sample}
     sw_plain = latency_stats(run_plain(requests(rate, switch_step=switch), dev))
-    all64_served = latency_stats(Server(dev, slots=3, max_batch=32).run(
+    all64_served = latency_stats(Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs).run(
         requests(rate, switch_step=0)))
     all64_plain = latency_stats(run_plain(requests(rate, switch_step=0), dev))
     # above capacity the switch shows in throughput: fp32 steps finish sooner
     hi = round(1.25 * cap, 1)
-    sw_hi = latency_stats(Server(dev, slots=3, max_batch=32).run(
+    sw_hi = latency_stats(Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs).run(
         requests(hi, switch_step=switch)))
-    all64_hi = latency_stats(Server(dev, slots=3, max_batch=32).run(
+    all64_hi = latency_stats(Server(dev, slots=3, max_batch=32, batch_flops=bf, call_streams=cs).run(
         requests(hi, switch_step=0)))
     host = {q: (state[q]["r64"][1].cpu().numpy(), state[q]["r64"][2].cpu().numpy())
             for q in sample}
@@ -220,7 +227,8 @@ def served_stream(args):
         for q, f in futs.items():
             f32_err[q] = checks.max_rel_err(f32_in[q][3], f.result())
     return {"workload": f"{nseq} sequences x {steps} solves, n ~ U{{1000..6000}}, nbw 64, "
-                        f"nev = n, Poisson arrivals; slots 3, max batch 32",
+                        f"nev = n, Poisson arrivals; slots 3, max batch 32, "
+                        f"batch work bound {bf:.3g} flops, {cs or 'library'} stream(s) per call",
             "plain_capacity_solves_per_s": cap,
             "graphs": {"prepared_batches": 2 * nseq, "device_bytes": gbytes,
                        "setup_s": round(gsetup, 2)},

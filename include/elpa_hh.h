@@ -36,6 +36,15 @@
  * executed the work.  Calls on different streams are independent and
  * thread-safe.
  *
+ * Workspace: a call takes its device workspace from the library's workspace
+ * cache (hipMalloc'd blocks kept per device after use; see
+ * elpa_hh_workspace_cached / elpa_hh_workspace_release).  A block is reused by
+ * a later call on the same stream at once and by a call on another stream
+ * only once the work that last used it has completed, so calls on different
+ * streams never wait for each other.  While a stream is being captured into a
+ * graph, the call's workspace is a stream-ordered allocation owned by the
+ * graph.
+ *
  * Errors: every call returns a status code, the counterpart of the error
  * out-argument that every call of the paper's C interface takes (Sec. 4.1,
  * the example use of the C interface); ELPA_OK = 0 is success.  Every
@@ -240,13 +249,18 @@ int elpa_hh_trafo_noalloc(int64_t n, int64_t nev, int64_t nbw, const void *hh,
  *   prepared form, i.e. other than the two-lane kernel, gives ELPA_ERR_PLAN),
  *   builds the same schedules, allocates the device workspace and tables on
  *   the current device (hipMalloc; ELPA_ERR_NOMEM if it cannot) and copies the
- *   tables there before returning (synchronous).  A single problem is
- *   prepared as the single-problem call (its stripe groups on library streams
- *   forked from the run's stream).  probs is read during the call; the
- *   problems' device pointers are kept and must stay valid until destroy.
+ *   tables there before returning (synchronous).  A batch in which exactly
+ *   one problem has work (n > 1, nev > 0) is prepared as the single-problem
+ *   call elpa_hh_trafo_plan(..., plan) makes: the same kernel choice (the
+ *   compact-WY kernel where the library picks it for a single call), plan
+ *   and stripe groups on library streams forked from the run's stream; a
+ *   family without a caller-workspace form (the one-lane kernel) gives
+ *   ELPA_ERR_PLAN.  probs is read during the call; the problems' device
+ *   pointers are kept and must stay valid until destroy.
  * elpa_hh_batch_run: the back-transformation of every problem of the batch
- *   on `stream`, with the results of elpa_hh_trafo_batched (bitwise, same
- *   kernels and schedule): kernel launches and event fork/join only, no
+ *   on `stream`, with the results of elpa_hh_trafo_batched, or for a batch of
+ *   one problem with work those of elpa_hh_trafo_plan (bitwise, same kernels
+ *   and schedule): kernel launches and event fork/join only, no
  *   allocation, no copy, no host synchronisation, so it may be captured into
  *   a graph.  Runs of one batch share its workspace: they must not overlap
  *   (one stream, or ordered by events).  ELPA_ERR_ARG on another device.
@@ -261,8 +275,8 @@ int64_t elpa_hh_batch_bytes(const elpa_hh_batch *batch);
 int elpa_hh_batch_destroy(elpa_hh_batch *batch);
 
 /*
- * Device workspace (bytes) that elpa_hh_trafo_plan allocates, in stream order,
- * for one problem under `plan` (NULL = library choice): the stripe-major copy
+ * Device workspace (bytes) that elpa_hh_trafo_plan takes from the workspace
+ * cache for one problem under `plan` (NULL = library choice): the stripe-major copy
  * of Q and, for paths 3 and 4, the packed reflectors.  0 for no-ops and the
  * reference path, -1 for invalid arguments or a plan that cannot run.  A
  * batched call allocates the sum over its problems plus small descriptor
@@ -270,6 +284,19 @@ int elpa_hh_batch_destroy(elpa_hh_batch *batch);
  */
 int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dtype,
                                 const elpa_hh_plan *plan);
+
+/*
+ * Workspace cache of the current device (see Workspace above):
+ * elpa_hh_workspace_cached returns the device bytes the cache holds (blocks in
+ * use and idle); elpa_hh_workspace_release frees the idle blocks whose last
+ * use has completed and returns the bytes freed (it may wait for the device,
+ * as hipFree does).  The cache keeps at most 8 GiB of idle blocks per device
+ * before it frees the least recently used ones, and frees all idle blocks
+ * before an allocation is reported as failed.  ELPA_ERR_DEVICE if there is no
+ * current device.
+ */
+int64_t elpa_hh_workspace_cached(void);
+int64_t elpa_hh_workspace_release(void);
 
 /*
  * Upper bound of the device workspace of elpa_hh_trafo_batched on the same

@@ -74,6 +74,10 @@ def library():
         L.elpa_hh_plan_supported.restype = C.c_int
         L.elpa_hh_workspace_bytes.argtypes = [i64, i64, i64, i32, C.POINTER(_Plan)]
         L.elpa_hh_workspace_bytes.restype = i64
+        L.elpa_hh_workspace_cached.argtypes = []
+        L.elpa_hh_workspace_cached.restype = i64
+        L.elpa_hh_workspace_release.argtypes = []
+        L.elpa_hh_workspace_release.restype = i64
         L.elpa_hh_workspace_bytes_batched.argtypes = [C.POINTER(_Problem), i64,
                                                       C.POINTER(_Plan)]
         L.elpa_hh_workspace_bytes_batched.restype = i64
@@ -246,6 +250,17 @@ def workspace_bytes(n, nev, nbw, dtype, path=None, k=0):
     pl = _plan(path, k)
     return int(library().elpa_hh_workspace_bytes(n, nev, nbw, dtype,
                                                  C.byref(pl) if pl is not None else None))
+
+
+def workspace_cached():
+    """Device bytes the library's workspace cache holds on the current device."""
+    return int(library().elpa_hh_workspace_cached())
+
+
+def workspace_release():
+    """Free the cache's idle workspace blocks on the current device (returns
+    the bytes freed)."""
+    return int(library().elpa_hh_workspace_release())
 
 
 def workspace_bytes_batched(problems, path=None, k=0):

@@ -14,7 +14,7 @@ OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libelpahip.so")
 # the stripe kernel families are split by element type so that their many
 # fully unrolled variants compile in parallel
-SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_kernels.hip", "hh_stripe_r64.hip",
+SOURCES = ["elpa_hh.cpp", "hh_tune.cpp", "hh_ws.cpp", "hh_kernels.hip", "hh_stripe_r64.hip",
            "hh_stripe_r32.hip", "hh_stripe_c64.hip", "hh_split.hip", "hh_split_r64.hip",
            "hh_split_r32.hip", "hh_split_c64.hip", "hh_wy.hip", "hh_wy_r64.hip",
            "hh_wy_r32.hip", "hh_wy_c64.hip", "bt2.hip", "b2t.hip", "f2b.hip",

@@ -228,6 +228,44 @@ struct elpa_hh_batch {
   std::vector<elpa_hh_problem> singles;
 };
 
+namespace {
+
+// One problem prepared as the single-problem call: the kernel the library
+// picks for a single call on a workspace allocated once.
+class SinglePrepared : public ehh::PreparedGroup {
+ public:
+  SinglePrepared(const elpa_hh_problem& p, const ehh::StripeEntry* se, ehh::TileOpts opt,
+                 int num_cu)
+      : p_(p), se_(se), opt_(opt), num_cu_(num_cu) {}
+  ~SinglePrepared() override {
+    if (ws_) (void)hipFree(ws_);
+  }
+  hipError_t init() {
+    bytes_ = se_->workspace(p_.n, p_.nev);
+    if (bytes_ == 0) return hipSuccess;
+    const hipError_t err = hipMalloc(&ws_, bytes_);
+    if (err != hipSuccess) {
+      ws_ = nullptr;
+      (void)hipGetLastError();
+    }
+    return err;
+  }
+  hipError_t run(hipStream_t st) override {
+    return se_->with_ws(p_.hh, p_.tau, p_.Q, p_.ldq, p_.n, p_.nev, opt_, st, num_cu_, ws_);
+  }
+  size_t bytes() const override { return bytes_; }
+
+ private:
+  elpa_hh_problem p_;
+  const ehh::StripeEntry* se_;
+  ehh::TileOpts opt_;
+  int num_cu_;
+  void* ws_ = nullptr;
+  size_t bytes_ = 0;
+};
+
+}  // namespace
+
 namespace ehh {
 ProfState& prof_state() {
   static thread_local ProfState s;
@@ -351,6 +389,42 @@ int elpa_hh_batch_create(const elpa_hh_problem* probs, int64_t count, const elpa
   std::map<const ehh::StripeEntry*, std::vector<int64_t>> groups;
   auto b = std::make_unique<elpa_hh_batch>();
   if (hipGetDevice(&b->dev) != hipSuccess) return ELPA_ERR_DEVICE;
+  const int cus = device_cus();
+  // one problem with work: the kernel and plan of the single-problem call
+  int64_t live = 0, one = -1;
+  for (int64_t i = 0; i < count; ++i)
+    if (probs[i].n > 1 && probs[i].nev > 0) ++live, one = i;
+  if (live == 1) {
+    const elpa_hh_problem& p = probs[one];
+    elpa_hh_plan tuned{};
+    const elpa_hh_plan* pp = effective_plan(p.dtype, p.nbw, p.n, p.nev, plan, &tuned);
+    int path = 0, rc = 0;
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, pp, &path, &rc, false, p.n);
+    if (rc != ELPA_OK) return rc;
+    // every problem's plan must resolve, as in the batched call
+    for (int64_t i = 0; i < count; ++i) {
+      if (i == one) continue;
+      elpa_hh_plan t2{};
+      const elpa_hh_plan* p2 =
+          effective_plan(probs[i].dtype, probs[i].nbw, probs[i].n, probs[i].nev, plan, &t2);
+      int path2 = 0;
+      (void)resolve(probs[i].dtype, probs[i].nbw, p2, &path2, &rc, true);
+      if (rc != ELPA_OK) return rc;
+    }
+    b->path = path;
+    if (!se) {
+      b->singles.push_back(p);
+    } else if (se->with_ws) {
+      auto g = std::make_unique<SinglePrepared>(p, se, tile_opts(pp), cus);
+      const hipError_t err = g->init();
+      if (err != hipSuccess) return status_of(err);
+      b->groups.emplace_back(std::move(g));
+    } else {
+      return ELPA_ERR_PLAN;
+    }
+    *out = b.release();
+    return ELPA_OK;
+  }
   int last_path = ELPA_PATH_REF;
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
@@ -370,7 +444,6 @@ int elpa_hh_batch_create(const elpa_hh_problem* probs, int64_t count, const elpa
     }
   }
   b->path = groups.size() + b->singles.size() == 1 ? last_path : ELPA_PATH_AUTO;
-  const int cus = device_cus();
   for (const ehh::StripeEntry* se : order) {
     const std::vector<int64_t>& ids = groups[se];
     ehh::PreparedGroup* g = nullptr;

@@ -463,7 +463,7 @@ hipError_t launch_diag(const void* hh, const void* tau, void* Q, int64_t ldq, in
     // stripe groups on concurrent streams (see the split kernel's launcher)
     StreamFork fork(st, ns);
     if (fork.error() != hipSuccess) {
-      (void)hipFreeAsync(Qs, st);
+      (void)ws_free(Qs, st);
       return fork.error();
     }
     for (int64_t t = 0; t < pl.T; ++t) {
@@ -484,13 +484,13 @@ hipError_t launch_diag(const void* hh, const void* tau, void* Q, int64_t ldq, in
   }
   prof.end();
   if (err != hipSuccess) {
-    (void)hipFreeAsync(Qs, st);
+    (void)ws_free(Qs, st);
     return err;
   }
   hipLaunchKernelGGL(k_from_rows<E>, dim3((unsigned)((n + 63) / 64), (unsigned)pl.G), dim3(256),
                      0, st, (const E*)Qs, pl.rows_pad, (E*)Q, ldq, n, nev);
   err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(Qs, st);
+  const hipError_t e2 = ws_free(Qs, st);
   return err != hipSuccess ? err : e2;
 }
 
@@ -578,7 +578,7 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
   if (err == hipSuccess && !ent.empty())
     err = stage.upload(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry), st);
   if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
+    (void)ws_free(ws, st);
     return err;
   }
   const ProblemDesc* dd = (const ProblemDesc*)ws;
@@ -597,7 +597,7 @@ hipError_t launch_diag_batched(const elpa_hh_problem* probs, const int64_t* idx,
   prof.end();
   hipLaunchKernelGGL(k_from_rows_b<E>, dim3((unsigned)otiles), dim3(256), 0, st, dd, count);
   err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(ws, st);
+  const hipError_t e2 = ws_free(ws, st);
   return err != hipSuccess ? err : e2;
 }
 

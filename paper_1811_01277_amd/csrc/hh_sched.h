@@ -118,29 +118,17 @@ __device__ __forceinline__ int zero_after(z64 d) { return zero_after(d.re); }
 
 inline size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-// Stream-ordered workspace allocation on the current device.  A request above
-// the device's total memory fails at once with hipErrorOutOfMemory, without
-// asking the allocator; a failed allocation leaves no error behind for the
-// next runtime call to report.
-inline hipError_t ws_alloc(void** p, size_t bytes, hipStream_t st) {
-  static std::mutex mu;
-  static std::vector<size_t> total;
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  {
-    std::lock_guard<std::mutex> g(mu);
-    if ((size_t)dev >= total.size()) total.resize((size_t)dev + 1, 0);
-    if (total[(size_t)dev] == 0) {
-      size_t t = 0;
-      if (hipDeviceTotalMem(&t, dev) == hipSuccess) total[(size_t)dev] = t;
-    }
-    if (total[(size_t)dev] != 0 && bytes > total[(size_t)dev]) return hipErrorOutOfMemory;
-  }
-  e = hipMallocAsync(p, bytes, st);
-  if (e != hipSuccess) (void)hipGetLastError();
-  return e;
-}
+// Workspace of one call on the current device, valid in the order of `st`:
+// a block of the library's workspace cache (hh_ws.cpp) that no pending work
+// uses, or, while `st` is being captured into a graph, a stream-ordered
+// allocation that the graph owns.  A request above the device's total memory
+// fails at once with hipErrorOutOfMemory; a failed allocation leaves no error
+// behind for the next runtime call to report.
+hipError_t ws_alloc(void** p, size_t bytes, hipStream_t st);
+// Returns a ws_alloc block after the work enqueued on `st` so far: the cache
+// hands it out again to later work on `st` at once, and to work on other
+// streams once that work has completed.
+hipError_t ws_free(void* p, hipStream_t st);
 
 // Stream-ordered host->device upload of small host tables.  hipMemcpyAsync
 // from pageable memory copies at call time, but a destination obtained from

@@ -458,7 +458,7 @@ hipError_t run_split(const void* hh, const void* tau, void* Q, int64_t ldq, int6
   }
   auto release = [&](hipError_t e) {
     if (!ws_in) {
-      const hipError_t e2 = hipFreeAsync(ws, st);
+      const hipError_t e2 = ws_free(ws, st);
       if (e == hipSuccess) e = e2;
     }
     return e;
@@ -743,12 +743,12 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
   if (err == hipSuccess && !B.ent.empty())
     err = stage.upload(ws + B.dbytes, B.ent.data(), B.ent.size() * sizeof(DiagEntry), st);
   if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
+    (void)ws_free(ws, st);
     return err;
   }
   launch_split_batch<E, NB, K, OCC, PD>(B, ws, opt.xcd, st);
   err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(ws, st);
+  const hipError_t e2 = ws_free(ws, st);
   return err != hipSuccess ? err : e2;
 }
 

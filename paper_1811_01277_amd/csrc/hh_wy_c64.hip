@@ -6,7 +6,8 @@ namespace ehh {
 
 #define EHH_WY(E, DT, NB, K, T, OCC, PF, VP)                                             \
   {ELPA_PATH_WY, DT, NB, K, OCC, &launch_wy<E, NB, K, T, OCC, PF, VP>,                 \
-   &launch_wy_batched<E, NB, K, T, OCC, PF, VP>, &wy_workspace<E, NB, K, T>, nullptr, nullptr}
+   &launch_wy_batched<E, NB, K, T, OCC, PF, VP>, &wy_workspace<E, NB, K, T>,          \
+   &launch_wy_ws<E, NB, K, T, OCC, PF, VP>, nullptr}
 
 const StripeEntry* wy_table_c64(int* size) {
   static const StripeEntry table[] = {

@@ -591,9 +591,12 @@ size_t wy_workspace(int64_t n, int64_t nev) {
   return wy_pbytes<E, NB, K>(n) + pl.template qbytes<E>();
 }
 
+// Single problem.  ws_in: a device workspace of at least
+// wy_workspace(n, nev) bytes that no other work uses while this call's work
+// runs, or null: then the workspace is allocated and freed in stream order.
 template <typename E, int NB, int K, int T, int OCC, bool PF, bool VP>
-hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
-                     int64_t nev, TileOpts opt, hipStream_t st, int num_cu) {
+hipError_t run_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
+                  int64_t nev, TileOpts opt, hipStream_t st, int num_cu, void* ws_in) {
   using Gm = WyGeom<NB, K>;
   using R = typename WyElem<E>::R;
   constexpr int SW = 16 * T;
@@ -604,9 +607,19 @@ hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int6
   if (pl.G * pl.M >= INT32_MAX || pl.M * Jmax * Gm::SG >= INT32_MAX || n + NB + K >= INT32_MAX)
     return hipErrorInvalidValue;
   const size_t rbytes = wy_rbytes<E, NB, K>(n), pbytes = wy_pbytes<E, NB, K>(n);
-  char* ws = nullptr;
-  hipError_t err = ws_alloc((void**)&ws, pbytes + pl.template qbytes<E>(), st);
-  if (err != hipSuccess) return err;
+  char* ws = (char*)ws_in;
+  hipError_t err = hipSuccess;
+  if (!ws_in) {
+    err = ws_alloc((void**)&ws, pbytes + pl.template qbytes<E>(), st);
+    if (err != hipSuccess) return err;
+  }
+  auto release = [&](hipError_t e) {
+    if (!ws_in) {
+      const hipError_t e2 = ws_free(ws, st);
+      if (e == hipSuccess) e = e2;
+    }
+    return e;
+  };
   R* Pk = (R*)ws;
   int64_t* Bt = (int64_t*)(ws + rbytes);
   E* Qs = (E*)(ws + pbytes);
@@ -619,10 +632,7 @@ hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int6
   ProfScope prof(st, K, S, ns);
   {
     StreamFork fork(st, ns);
-    if (fork.error() != hipSuccess) {
-      (void)hipFreeAsync(ws, st);
-      return fork.error();
-    }
+    if (fork.error() != hipSuccess) return release(fork.error());
     for (int64_t t = 0; t < pl.T; ++t) {
       int64_t m0, cnt;
       pl.active(t, &m0, &cnt);
@@ -639,15 +649,22 @@ hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int6
     err = fork.join();
   }
   prof.end();
-  if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
-    return err;
-  }
+  if (err != hipSuccess) return release(err);
   hipLaunchKernelGGL((k_from_rows_sw<E, SW>), dim3((unsigned)((n + 63) / 64), gt), dim3(256), 0,
                      st, (const E*)Qs, pl.rows_pad, (E*)Q, ldq, n, nev, pl.G);
-  err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(ws, st);
-  return err != hipSuccess ? err : e2;
+  return release(hipGetLastError());
+}
+
+template <typename E, int NB, int K, int T, int OCC, bool PF, bool VP>
+hipError_t launch_wy(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
+                     int64_t nev, TileOpts opt, hipStream_t st, int num_cu) {
+  return run_wy<E, NB, K, T, OCC, PF, VP>(hh, tau, Q, ldq, n, nev, opt, st, num_cu, nullptr);
+}
+
+template <typename E, int NB, int K, int T, int OCC, bool PF, bool VP>
+hipError_t launch_wy_ws(const void* hh, const void* tau, void* Q, int64_t ldq, int64_t n,
+                        int64_t nev, TileOpts opt, hipStream_t st, int num_cu, void* ws) {
+  return run_wy<E, NB, K, T, OCC, PF, VP>(hh, tau, Q, ldq, n, nev, opt, st, num_cu, ws);
 }
 
 // Batched: problems idx[0..cnt) of probs (element type E, semi-bandwidth NB,
@@ -742,7 +759,7 @@ hipError_t launch_wy_batched(const elpa_hh_problem* probs, const int64_t* idx, i
   if (err == hipSuccess && !ent.empty())
     err = stage.upload(ws + dbytes, ent.data(), ent.size() * sizeof(DiagEntry), st);
   if (err != hipSuccess) {
-    (void)hipFreeAsync(ws, st);
+    (void)ws_free(ws, st);
     return err;
   }
   const ProblemDesc* dd = (const ProblemDesc*)ws;
@@ -764,7 +781,7 @@ hipError_t launch_wy_batched(const elpa_hh_problem* probs, const int64_t* idx, i
   hipLaunchKernelGGL((k_from_rows_sw_b<E, SW>), dim3((unsigned)otiles), dim3(256), 0, st, dd,
                      count);
   err = hipGetLastError();
-  const hipError_t e2 = hipFreeAsync(ws, st);
+  const hipError_t e2 = ws_free(ws, st);
   return err != hipSuccess ? err : e2;
 }
 

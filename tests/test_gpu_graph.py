@@ -66,19 +66,23 @@ def test_graph_replay_equals_eager(torch_dev, dt, path):
             assert torch.isfinite(junk)
 
 
-@pytest.mark.parametrize("sched", ["one_launch", "diagonal", "single"])
+@pytest.mark.parametrize("sched", ["one_launch", "diagonal", "single", "single_wy"])
 def test_prepared_batch_graph_replay_equals_eager(torch_dev, sched):
     """A prepared batch (elpa_hh_batch_create: tables and workspace on the
     device once) captured into a graph: every replay, with fresh input and
     other eager work in between, equals the eager batched call bitwise.
     Schedules: the one-launch and diagonal batched forms, and a single
-    problem (its stripe groups forked and joined inside the capture)."""
+    problem (the single-call kernel choice, compact-WY here for complex and
+    for fp64 at n >= 3000, its stripe groups forked and joined inside the
+    capture), which equals the single-problem call bitwise."""
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
     spec = {"one_launch": [(300, 64, 120, "r64"), (520, 64, 70, "r64"), (200, 64, 200, "r64")],
             "diagonal": [(300, 32, 120, "r32"), (700, 32, 90, "r32")],
-            "single": [(900, 64, 400, "c64")]}[sched]
-    batch = {"one_launch": P.BATCH_ONE_LAUNCH, "diagonal": P.BATCH_DIAGONAL, "single": 0}[sched]
+            "single": [(900, 64, 400, "c64")],
+            "single_wy": [(3100, 64, 300, "r64")]}[sched]
+    batch = {"one_launch": P.BATCH_ONE_LAUNCH, "diagonal": P.BATCH_DIAGONAL, "single": 0,
+             "single_wy": 0}[sched]
     tdt = {"r64": torch.float64, "r32": torch.float32, "c64": torch.complex128}
     probs, inputs = [], []
     for i, (n, nbw, nev, dt) in enumerate(spec):
@@ -92,11 +96,15 @@ def test_prepared_batch_graph_replay_equals_eager(torch_dev, sched):
         q = zs[0].clone()
         probs.append((q, h, t, nbw))
         inputs.append(zs)
-    # eager reference: the plain batched call on each input set
+    # eager reference: the plain batched call on each input set; a batch of
+    # one problem runs the single-problem call (the library's kernel choice)
     eager = []
     for r in range(3):
         cur = [(zs[r].clone(), h, t, nbw) for zs, (_, h, t, nbw) in zip(inputs, probs)]
-        P.hh_trafo_batched(cur, batch=batch)
+        if len(cur) == 1:
+            P.hh_trafo(*cur[0])
+        else:
+            P.hh_trafo_batched(cur, batch=batch)
         eager.append([c[0] for c in cur])
     torch.cuda.synchronize()
     B = P.Batch(probs, batch=batch)

@@ -197,11 +197,17 @@ def test_served_with_graphs_equals_alone(torch_dev):
     print("served with graphs", latency_stats(reqs), "replays", srv.replays, "held", held,
           flush=True)
     assert srv.replays > 0 and held > 0
+    vias = {r.via for r in reqs}
+    assert "graph" in vias and vias <= {"graph", "single", "batched"}
     for i, r in enumerate(reqs):
         q = inputs[i].t().contiguous().t()
-        # graphs and batches run the two-lane kernel; the bitwise comparison is
-        # with that kernel alone
-        P.hh_trafo(q, r.hh, r.tau, r.nbw, path=P.PATH_SPLIT)
+        # a replay or a lone call runs the library's single-call kernel; a
+        # batched call runs the two-lane kernel, bitwise equal to that kernel
+        # called alone
+        if r.via == "batched":
+            P.hh_trafo(q, r.hh, r.tau, r.nbw, path=P.PATH_SPLIT)
+        else:
+            P.hh_trafo(q, r.hh, r.tau, r.nbw)
         torch.cuda.synchronize()
-        assert torch.equal(q, r.q), i
+        assert torch.equal(q, r.q), (i, r.via)
     srv.close_graphs()
