@@ -252,7 +252,7 @@ def served_stream(args):
                     for q in sample}}}
 
 
-def batched_workload(quick=False):
+def batched_workload(quick=False, order=0):
     """The batched workload: 256 real fp64 problems, n_i ~ U{200..2000}
     (seed 401), nbw 32, nev = n_i, all back-transforms in one batched call
     (inputs drawn on the device).  Timed with the library's default plan, then
@@ -285,7 +285,7 @@ def batched_workload(quick=False):
 
     P.tuner_clear()
     P.profile_enable(True)
-    t_default = timed(lambda: P.hh_trafo_batched(probs))
+    t_default = timed(lambda: P.hh_trafo_batched(probs, order=order if quick else 0))
     pr = P.profile_last()
     P.profile_enable(False)
     if quick:
@@ -294,6 +294,8 @@ def batched_workload(quick=False):
                 "ms_default": round(t_default, 3), "launches": pr["launches"],
                 "kernel_ms": round(pr["kernel_ms"], 3)}
     t_single = timed(lambda: [P.hh_trafo(q, h, t, nbw) for (q, h, t, nbw) in probs], reps=1)
+    # the one launch with the stripes in plain problem order (no die grouping)
+    t_linear = timed(lambda: P.hh_trafo_batched(probs, order=P.ORDER_LINEAR))
     # one uniform plan timed over the whole batch
     t0 = time.perf_counter()
     plan = P.tune_batched(probs, level=1)
@@ -312,6 +314,7 @@ def batched_workload(quick=False):
             "gflops_default": round(flops / t_default / 1e6, 1),
             "ms_default": round(t_default, 3), "launches_default": pr["launches"],
             "kernel_ms_default": round(pr["kernel_ms"], 3),
+            "ms_linear_order": round(t_linear, 3),
             "gflops_tuned": round(flops / t_tuned / 1e6, 1), "ms_tuned": round(t_tuned, 3),
             "tuned_plan": plan, "tuning_s": round(tune_s, 1),
             "gflops_per_class_single_call_plans": round(flops / t_class / 1e6, 1),
@@ -784,7 +787,8 @@ def main():
         print(json.dumps({"served_stream": served_stream(args)}), flush=True)
         return
     if args.batched_only:
-        print(json.dumps({"batched_workload": batched_workload(quick=True)}), flush=True)
+        print(json.dumps({"batched_workload": batched_workload(quick=True, order=args.order)}),
+              flush=True)
         return
     if args.bt2_only:
         print(json.dumps({"bt2": bt2_leg(args, [args.nev])}), flush=True)

@@ -95,7 +95,10 @@ enum {
                              and fp32, nbw 32 or 64) */
 };
 
-/* order of the tiles of one launch over the workgroup ids (elpa_hh_plan.order) */
+/* order of the tiles of one launch over the workgroup ids (elpa_hh_plan.order).
+   The one-launch batched schedule deals each problem's stripes to one die
+   (dies balanced by work, longest problems first) unless ELPA_ORDER_LINEAR,
+   which numbers the stripes problem by problem in id order. */
 enum {
     ELPA_ORDER_AUTO = 0,   /* library choice */
     ELPA_ORDER_LINEAR = 1, /* tile (block m, stripe c) at id (m - m0) * stripes + c */

@@ -179,6 +179,7 @@ ehh::TileOpts tile_opts(const elpa_hh_plan* plan) {
   // two stripe groups by default: one group's launch tails overlap the other's
   o.streams = (plan && plan->streams > 0) ? plan->streams : 2;
   o.batch = plan ? plan->batch : ELPA_BATCH_AUTO;
+  o.order = plan ? plan->order : ELPA_ORDER_AUTO;
   return o;
 }
 
@@ -551,7 +552,7 @@ int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dty
 int64_t elpa_hh_workspace_bytes_batched(const elpa_hh_problem* probs, int64_t count,
                                         const elpa_hh_plan* plan) {
   if (count < 0 || (count > 0 && !probs)) return -1;
-  int64_t total = 0, launches = 0, groups = 0;
+  int64_t total = 0, launches = 0, groups = 0, units = 0;
   for (int64_t i = 0; i < count; ++i) {
     const elpa_hh_problem& p = probs[i];
     if (p.n < 0 || p.nev < 0 || p.nbw < 1 || elem_size(p.dtype) == 0) return -1;
@@ -565,10 +566,12 @@ int64_t elpa_hh_workspace_bytes_batched(const elpa_hh_problem* probs, int64_t co
     ++groups;
     // schedule entries: at most one per problem and launch (S >= 1)
     launches += (p.n - 1 + se->k - 1) / se->k + (p.n - 1 + p.nbw - 1) / p.nbw;
+    units += (p.nev + 15) / 16;  // stripes (at least 16 columns each)
   }
   if (groups == 0) return 0;
   const int64_t desc = 256;  // generous bound of one descriptor / entry
-  return total + (groups + launches) * desc + 4096;
+  // one-launch unit map: at most 8 ids (one per die) per stripe, 4 bytes each
+  return total + (groups + launches) * desc + units * 32 + 4096;
 }
 
 int elpa_hh_profile_enable(int on) {

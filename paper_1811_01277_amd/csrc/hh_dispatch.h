@@ -20,6 +20,8 @@ struct TileOpts {
   int xcd;
   int streams;
   int batch;  // ELPA_BATCH_* (batched calls of the two-lane kernel)
+  int order;  // ELPA_ORDER_* as given (the one-launch batched schedule groups
+              // each problem's stripes on one die unless ELPA_ORDER_LINEAR)
 };
 
 using StripeLaunch = hipError_t (*)(const void* hh, const void* tau, void* Q, int64_t ldq,

@@ -399,11 +399,15 @@ __global__ __launch_bounds__(64, OCC) void k_split_b(const ProblemDesc* __restri
 // K even, so a lane keeps its column and row parity), so no workgroup waits
 // for another.  Units are numbered problem by problem in the order of the
 // descriptor table (the host sorts it by decreasing work), so the dispatcher
-// starts the longest units first.
+// starts the longest units first.  umap (optional) gives the unit of each
+// workgroup id, -1 for none: the host deals each problem's stripes to one
+// die (workgroup ids go to the dies round robin), so the stripes that read a
+// problem's step records run side by side on one die's L2.
 template <typename E, int NB, int K, int OCC, int PD>
 __global__ __launch_bounds__(64, OCC) void k_split_seq(const ProblemDesc* __restrict__ d,
-                                                       int count) {
-  const int u = (int)blockIdx.x;
+                                                       int count, const int* __restrict__ umap) {
+  const int u = umap ? umap[blockIdx.x] : (int)blockIdx.x;
+  if (u < 0) return;
   const ProblemDesc& D = d[find_by<ProblemDesc, &ProblemDesc::unit0>(d, count, u)];
   const int64_t c = u - D.unit0;
   for (int64_t m = D.M - 1; m >= 0; --m)
@@ -563,7 +567,9 @@ struct SplitBatchPlan {
   std::vector<DiagEntry> ent;
   std::vector<int64_t> eoff, etiles;
   std::vector<size_t> pat, qat, rbytes;
-  size_t dbytes = 0, ebytes = 0, total = 0, tiles = 0, otiles = 0, ptiles = 0, units = 0;
+  std::vector<int> umap;  // one-launch schedule: unit of each workgroup id (-1: none)
+  size_t dbytes = 0, ebytes = 0, ubytes = 0, total = 0, tiles = 0, otiles = 0, ptiles = 0,
+         units = 0;
   int64_t T = 0;
   int K = 0;
   bool one_launch = false;
@@ -675,18 +681,39 @@ hipError_t plan_split_batch(const elpa_hh_problem* probs, const int64_t* idx, in
     return hipErrorInvalidValue;
   for (int64_t x : B.etiles)
     if (x >= INT32_MAX) return hipErrorInvalidValue;
+  if (B.one_launch && opt.order != ELPA_ORDER_LINEAR) {
+    // deal whole problems to the dies, longest first, each to the die with
+    // the least work so far; die x runs workgroup ids x, x + dies, ...
+    constexpr int dies = 8;
+    std::vector<std::vector<int>> lists(dies);
+    std::vector<double> load(dies, 0.0);
+    for (size_t i = 0; i < B.d.size(); ++i) {
+      const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[(size_t)x] += (double)B.d[i].G * (double)work(live[i]);
+      for (int c = 0; c < B.d[i].G; ++c) lists[(size_t)x].push_back(B.d[i].unit0 + c);
+    }
+    size_t len = 0;
+    for (const auto& l : lists) len = std::max(len, l.size());
+    if (len * dies >= (size_t)INT32_MAX) return hipErrorInvalidValue;
+    B.umap.assign(len * dies, -1);
+    for (int x = 0; x < dies; ++x)
+      for (size_t i = 0; i < lists[(size_t)x].size(); ++i)
+        B.umap[i * dies + (size_t)x] = lists[(size_t)x][i];
+  }
   B.dbytes = align256(B.d.size() * sizeof(ProblemDesc));
   B.ebytes = align256(std::max<size_t>(1, B.ent.size()) * sizeof(DiagEntry));
-  B.total = B.dbytes + B.ebytes + off;
+  B.ubytes = align256(B.umap.size() * sizeof(int));
+  B.total = B.dbytes + B.ebytes + B.ubytes + off;
   return hipSuccess;
 }
 
 // Device addresses of the plan's areas in a workspace of B.total bytes.
 inline void bind_split_batch(SplitBatchPlan& B, char* ws) {
   for (size_t i = 0; i < B.d.size(); ++i) {
-    B.d[i].P = ws + B.dbytes + B.ebytes + B.pat[i];
-    B.d[i].Bt = ws + B.dbytes + B.ebytes + B.pat[i] + B.rbytes[i];
-    B.d[i].Qs = ws + B.dbytes + B.ebytes + B.qat[i];
+    char* area = ws + B.dbytes + B.ebytes + B.ubytes;
+    B.d[i].P = area + B.pat[i];
+    B.d[i].Bt = area + B.pat[i] + B.rbytes[i];
+    B.d[i].Qs = area + B.qat[i];
   }
 }
 
@@ -706,8 +733,10 @@ void launch_split_batch(const SplitBatchPlan& B, const char* ws, int xcd, hipStr
     ProfScope prof(st, K, 0);
     if (B.one_launch) {
       prof.before(st);
-      hipLaunchKernelGGL((k_split_seq<E, NB, K, OCC, PD>), dim3((unsigned)B.units), dim3(64), 0,
-                         st, dd, count);
+      const int* um = B.umap.empty() ? nullptr : (const int*)(ws + B.dbytes + B.ebytes);
+      const size_t grid = B.umap.empty() ? B.units : B.umap.size();
+      hipLaunchKernelGGL((k_split_seq<E, NB, K, OCC, PD>), dim3((unsigned)grid), dim3(64), 0, st,
+                         dd, count, um);
       prof.after(st);
     } else {
       for (int64_t t = 0; t < B.T; ++t) {
@@ -742,6 +771,8 @@ hipError_t launch_split_batched(const elpa_hh_problem* probs, const int64_t* idx
   err = stage.upload(ws, B.d.data(), B.d.size() * sizeof(ProblemDesc), st);
   if (err == hipSuccess && !B.ent.empty())
     err = stage.upload(ws + B.dbytes, B.ent.data(), B.ent.size() * sizeof(DiagEntry), st);
+  if (err == hipSuccess && !B.umap.empty())
+    err = stage.upload(ws + B.dbytes + B.ebytes, B.umap.data(), B.umap.size() * sizeof(int), st);
   if (err != hipSuccess) {
     (void)ws_free(ws, st);
     return err;
@@ -788,6 +819,9 @@ class SplitPrepared : public PreparedGroup {
     if (err == hipSuccess && !B_.ent.empty())
       err = hipMemcpy((char*)ws_ + B_.dbytes, B_.ent.data(), B_.ent.size() * sizeof(DiagEntry),
                       hipMemcpyHostToDevice);
+    if (err == hipSuccess && !B_.umap.empty())
+      err = hipMemcpy((char*)ws_ + B_.dbytes + B_.ebytes, B_.umap.data(),
+                      B_.umap.size() * sizeof(int), hipMemcpyHostToDevice);
     return err;
   }
   hipError_t run(hipStream_t st) override {

@@ -50,11 +50,15 @@ def rounded(x, dt):
     return x.astype(np.float32).astype(np.float64) if dt == "r32" else x
 
 
-@pytest.mark.parametrize("sched", ["one_launch", "diagonal", "auto"])
+@pytest.mark.parametrize("sched", ["one_launch", "one_launch_linear", "diagonal", "auto"])
 def test_batch_matches_oracle_and_single_calls(torch_dev, sched):
+    """one_launch deals each problem's stripes to one die (the default order);
+    one_launch_linear numbers them problem by problem in workgroup order."""
     torch, dev = torch_dev
     import paper_1811_01277_amd as P
-    batch = {"one_launch": P.BATCH_ONE_LAUNCH, "diagonal": P.BATCH_DIAGONAL, "auto": 0}[sched]
+    batch = {"one_launch": P.BATCH_ONE_LAUNCH, "one_launch_linear": P.BATCH_ONE_LAUNCH,
+             "diagonal": P.BATCH_DIAGONAL, "auto": 0}[sched]
+    order = P.ORDER_LINEAR if sched == "one_launch_linear" else 0
     sizes = [(65, 32, 65), (200, 32, 200), (333, 32, 101), (97, 32, 97), (512, 32, 512),
              (130, 64, 129), (260, 64, 64)]
     probs, host = [], []
@@ -71,14 +75,14 @@ def test_batch_matches_oracle_and_single_calls(torch_dev, sched):
     print("batch of", len(probs), "problems", flush=True)
     P.profile_enable(True)
     try:
-        P.hh_trafo_batched(probs, batch=batch)
+        P.hh_trafo_batched(probs, batch=batch, order=order)
         pr = P.profile_last()
     finally:
         P.profile_enable(False)
     torch.cuda.synchronize()
     # every problem runs the two-lane kernel: one group per nbw (32 and 64),
     # each one launch or its diagonal sequence
-    if sched == "one_launch":
+    if sched.startswith("one_launch"):
         assert pr["launches"] == 2, pr
     elif sched == "diagonal":
         assert pr["launches"] > 2, pr
