@@ -120,6 +120,10 @@ enum {
  * 0 = library choice, 2); batch: schedule of the two-lane kernel in batched
  * calls, ELPA_BATCH_* (single-problem calls ignore it).
  * Results do not depend on order, streams or batch.
+ * A plan that leaves the kernel open (path AUTO, k, steps and batch 0, or
+ * NULL) runs the tuner's plan for the problem's size class when there is one
+ * (elpa_hh_tune, elpa_hh_tuner_*), with the caller's order and streams where
+ * those are set.
  */
 typedef struct {
     int32_t path;

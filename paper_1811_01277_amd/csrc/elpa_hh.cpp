@@ -160,15 +160,18 @@ int device_cus() {
   return cache[dev];
 }
 
-// The plan a call runs: the caller's explicit plan, else the tuner's plan for
-// the size class of (n, nev) if there is one, else NULL (library choice).
+// The plan a call runs.  A plan that leaves the kernel open (path AUTO, k,
+// steps and batch 0; NULL included) takes the tuner's plan for the size
+// class of (n, nev) if there is one, with the caller's order and streams
+// where those are set; otherwise the caller's plan (NULL: library choice).
 const elpa_hh_plan* effective_plan(int32_t dtype, int64_t nbw, int64_t n, int64_t nev,
                                    const elpa_hh_plan* plan, elpa_hh_plan* buf) {
-  const bool automatic = !plan || (plan->path == ELPA_PATH_AUTO && plan->k == 0 &&
-                                   plan->steps == 0 && plan->order == 0 && plan->streams == 0 &&
-                                   plan->batch == 0);
-  if (automatic && ehh::tuner_lookup(dtype, nbw, n, nev, buf)) return buf;
-  return plan;
+  const bool open = !plan || (plan->path == ELPA_PATH_AUTO && plan->k == 0 &&
+                              plan->steps == 0 && plan->batch == 0);
+  if (!open || !ehh::tuner_lookup(dtype, nbw, n, nev, buf)) return plan;
+  if (plan && plan->order != 0) buf->order = plan->order;
+  if (plan && plan->streams != 0) buf->streams = plan->streams;
+  return buf;
 }
 
 // Tile options of a plan (NULL = library choice).

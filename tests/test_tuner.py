@@ -135,3 +135,21 @@ def test_autotune_setup_levels_fixed_and_state_round_trip(tmp_path):
         P.Autotune(5, 1000, 1000, 64, P.R64)
     with pytest.raises(P.ElpaError):
         P.Autotune(P.AUTOTUNE_FAST, 1000, 1000, 64, P.R64, path=P.PATH_WY, k=63)
+
+
+def test_plan_with_only_streams_set_takes_tuned_kernel():
+    """A plan that sets only streams (or order) leaves the kernel open: it runs
+    the tuned plan's kernel, so its workspace is that plan's."""
+    import ctypes as C
+    from paper_1811_01277_amd import binding as B
+    n, nev = 20000, 20000
+    wy = P.workspace_bytes(n, nev, 64, P.R64, path=P.PATH_WY, k=32)
+    streams_only = B._Plan(0, 0, 0, 0, 1, 0)
+    lib = B.library()
+    before = lib.elpa_hh_workspace_bytes(n, nev, 64, P.R64, C.byref(streams_only))
+    assert before != wy
+    P.tuner_set(P.R64, 64, n, nev, path=P.PATH_WY, k=32)
+    assert lib.elpa_hh_workspace_bytes(n, nev, 64, P.R64, C.byref(streams_only)) == wy
+    # an explicit kernel field keeps the caller's plan
+    k80 = B._Plan(0, 80, 0, 0, 1, 0)
+    assert lib.elpa_hh_workspace_bytes(n, nev, 64, P.R64, C.byref(k80)) != wy
