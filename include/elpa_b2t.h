@@ -39,6 +39,11 @@ extern "C" {
  * Asynchronous on `stream` (a hipStream_t; NULL = the null stream); about
  * 3 n kernel launches, each a bounded set of independent chase steps (steps
  * that touch disjoint entries), in an order equal to the sequential one.
+ * Real bands with nbw <= 64 stage each step's blocks in LDS and update only
+ * the lower triangle (the symmetric two-sided update of the diagonal block
+ * as a rank-2 update), reading only A's lower triangle; the upper triangle
+ * is written once at the end.  Complex bands and wider real bands update
+ * both triangles step by step.
  * Returns ELPA_OK or ELPA_ERR_ARG / _DTYPE / _ALIGN / _DEVICE (elpa_hh.h);
  * arguments are checked before anything is enqueued; n == 1 writes d only.
  */

@@ -69,6 +69,26 @@ def test_b2t_matches_oracle(torch_dev, case, cplx):
 
 
 @pytest.mark.parametrize("cplx", [False, True])
+@pytest.mark.parametrize("nb", [64, 96])
+def test_b2t_leaves_the_tridiagonal_matrix(torch_dev, cplx, nb):
+    """On return A holds the tridiagonal matrix (d, e) in both triangles and
+    zeros elsewhere (the real path with nbw <= 64 updates only the lower
+    triangle during the chase and rebuilds the upper one at the end)."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    n = 260
+    B = band_matrix(n, nb, cplx, 430)
+    a = torch.from_numpy(np.ascontiguousarray(B.T)).to(dev).t()
+    d, e, hh, tau = P.band_to_tridiag(a, nb)
+    torch.cuda.synchronize()
+    d, e, Ar = d.cpu().numpy(), e.cpu().numpy(), a.cpu().numpy()
+    T = np.diag(d) + np.diag(e, -1) + np.diag(e, 1)
+    assert np.max(np.abs(Ar - T)) <= 1e-12 * float(np.max(np.abs(B)))
+    d0, e0, _, _ = stage2.band_to_tridiag(B, nb)
+    assert np.max(np.abs(d - d0)) <= 1e-12 * float(np.max(np.abs(B))) * n ** 0.5
+
+
+@pytest.mark.parametrize("cplx", [False, True])
 def test_device_reflectors_drive_back_transform(torch_dev, cplx):
     """d, e from the GPU -> tridiagonal eigenvectors (oracle) -> elpa_hh_trafo
     with the GPU's hh / tau, never copied to the host: the band eigenvectors
