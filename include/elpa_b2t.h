@@ -39,7 +39,7 @@ extern "C" {
  * Asynchronous on `stream` (a hipStream_t; NULL = the null stream); about
  * 3 n kernel launches, each a bounded set of independent chase steps (steps
  * that touch disjoint entries), in an order equal to the sequential one.
- * Real bands with nbw <= 64 stage each step's blocks in LDS and update only
+ * Real bands with nbw <= 64 hold each step's blocks in registers and update only
  * the lower triangle (the symmetric two-sided update of the diagonal block
  * as a rank-2 update), reading only A's lower triangle; the upper triangle
  * is written once at the end.  Complex bands and wider real bands update

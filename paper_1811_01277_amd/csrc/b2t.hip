@@ -246,29 +246,29 @@ __global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, i
   if (tid == 0) tau[slot] = tv;
 }
 
-// Real band, nb <= 64: the same steps with every value a step reads staged in
-// LDS and only the lower triangle updated (the upper triangle is rebuilt at
-// the end from the tridiagonal result).  A step (s, j) with H = I - tau v v^T
-// on the indices [r, r+L) changes three lower-triangle blocks:
+// Real band, nb <= 64: the same steps on the lower triangle only, every value
+// a step touches held in registers (the upper triangle is rebuilt at the end
+// from the tridiagonal result).  A step (s, j) with H = I - tau v v^T on the
+// indices [r, r+L) changes three lower-triangle blocks:
 //   R = rows [r, r+L) x columns [c0, r)   <- H R   (c0 = s for j = 0: the
 //       columns left of s are already reduced and zero in these rows; else
 //       r - nb, the bulge columns)
 //   D = rows and columns [r, r+L)         <- H D H (symmetric; with y = D v,
 //       mu = v^T y and w = tau y - tau^2 mu / 2 v: D <- D - w v^T - v w^T)
 //   C = rows [r+L, hi) x columns [r, r+L) <- C H   (hi = min(r+L+nb, n))
-// Each block is loaded whole (every thread's loads issued before any value is
-// used), updated in LDS and stored once.  The lower triangle the steps touch
-// is a subset of the entries of the two-sided form above, so the launch
-// schedule's disjointness holds unchanged.
-constexpr int kLd = 65;  // LDS leading dimension (column major, padded)
-
-__global__ __launch_bounds__(256) void k_chase_lds(double* __restrict__ A, int64_t lda, int64_t n,
+// Lane i of every wave holds row i of each block, wave w the columns w, w+4,
+// ..., so each block is one coalesced load per column, all issued before any
+// value is used, and one store.  Column sums (v^T R, the strictly-lower part
+// of D^T v) are wave reductions; row sums (the lower part of D v, C v) add
+// the four waves' partial sums through LDS.  Two barriers per step.  The
+// lower-triangle entries the steps touch are a subset of the two-sided form's,
+// so the launch schedule's disjointness holds unchanged.
+__global__ __launch_bounds__(256) void k_chase_reg(double* __restrict__ A, int64_t lda, int64_t n,
                                                    int64_t nb, int64_t t, int64_t s_lo,
                                                    double* __restrict__ hh,
                                                    double* __restrict__ tau) {
-  __shared__ double Rb[64 * kLd], Db[64 * kLd], Cb[64 * kLd];
-  __shared__ double vs[64], ys[64], ws[64], us[64];
-  __shared__ double sh_tau, sh_beta;
+  __shared__ double vs[64], ys2[64], py[4][64], pu[4][64];
+  __shared__ double sh_tau;
   const int64_t s = s_lo + blockIdx.x;
   const int64_t j = t - kLag * s;
   const int64_t r = s + 1 + j * nb;
@@ -279,28 +279,18 @@ __global__ __launch_bounds__(256) void k_chase_lds(double* __restrict__ A, int64
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto at = [&](int64_t i, int64_t k) -> double& { return A[i + k * lda]; };
 
-  // load R, D, C: lanes over rows (coalesced), waves over columns
-  {
-    double xr[16], xd[16], xc[16];
+  double xr[16], xd[16], xc[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = wave + 4 * q;
-      xr[q] = (lane < L && k < nR) ? at(r + lane, c0 + k) : 0.0;
-      xd[q] = (lane < L && k < L && lane >= k) ? at(r + lane, r + k) : 0.0;
-      xc[q] = (lane < nC && k < L) ? at(r + L + lane, r + k) : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = wave + 4 * q;
-      Rb[k * kLd + lane] = xr[q];
-      Db[k * kLd + lane] = xd[q];
-      Cb[k * kLd + lane] = xc[q];
-    }
+  for (int q = 0; q < 16; ++q) {
+    const int k = wave + 4 * q;
+    xr[q] = (lane < L && k < nR) ? at(r + lane, c0 + k) : 0.0;
+    xd[q] = (lane < L && k < L && lane >= k) ? at(r + lane, r + k) : 0.0;
+    xc[q] = (lane < nC && k < L) ? at(r + L + lane, r + k) : 0.0;
   }
-  __syncthreads();
-  // reflector from column 0 of R (column c0, the column this step reduces)
+  // reflector from column 0 of R (column c0, the column this step reduces;
+  // wave 0's first column)
   if (wave == 0) {
-    const double x = lane < L ? Rb[lane] : 0.0;
+    const double x = xr[0];
     const double ss = wave_sum(lane >= 1 ? x * x : 0.0);
     const double alpha = __shfl(x, 0, 64);
     double tv = 0.0, beta = alpha, sc = 0.0;
@@ -311,72 +301,64 @@ __global__ __launch_bounds__(256) void k_chase_lds(double* __restrict__ A, int64
       sc = 1.0 / (alpha - beta);
     }
     vs[lane] = lane == 0 ? 1.0 : (lane < L ? x * sc : 0.0);
-    Rb[lane] = (lane == 0) ? beta : 0.0;   // the reduced column, exactly
-    if (lane == 0) {
-      sh_tau = tv;
-      sh_beta = beta;
-    }
+    xr[0] = lane == 0 ? beta : 0.0;   // the reduced column, exactly
+    if (lane == 0) sh_tau = tv;
   }
   __syncthreads();
   const double tv = sh_tau;
-  if (tv != 0.0) {
-    // R <- H R (columns 1 .. nR-1); y = D v and u = tau C v
-    const double vl = vs[lane];
-    for (int k = 1 + wave; k < nR; k += 4) {
-      const double x = Rb[k * kLd + lane];
-      const double w = tv * wave_sum(vl * x);
-      if (lane < L) Rb[k * kLd + lane] = x - vl * w;
-    }
-    {
-      const int i = tid >> 2, part = tid & 3;
-      double ay = 0.0, au = 0.0;
+  const double vl = vs[lane];
+  double vk[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) {
-        const int k = part * 16 + u;
-        const double dik = i >= k ? Db[k * kLd + i] : Db[i * kLd + k];
-        ay += dik * vs[k];
-        au += Cb[k * kLd + i] * vs[k];
-      }
-      ay += __shfl_xor(ay, 1, 64);
-      ay += __shfl_xor(ay, 2, 64);
-      au += __shfl_xor(au, 1, 64);
-      au += __shfl_xor(au, 2, 64);
-      if (part == 0) {
-        ys[i] = ay;
-        us[i] = tv * au;
-      }
-    }
-    __syncthreads();
-    if (wave == 0) {
-      const double mu = wave_sum(vs[lane] * ys[lane]);
-      ws[lane] = tv * ys[lane] - 0.5 * tv * tv * mu * vs[lane];
-    }
-    __syncthreads();
-    // D <- D - w v^T - v w^T (lower), C <- C - u v^T
+  for (int q = 0; q < 16; ++q) vk[q] = vs[wave + 4 * q];
+  if (tv != 0.0) {
+    // column sums: v^T R (R's update) and the strictly lower part of D^T v;
+    // row sums: the lower part of D v and C v, per wave
+    double wr[16];
+    double ry = 0.0, ru = 0.0;
 #pragma unroll
     for (int q = 0; q < 16; ++q) {
       const int k = wave + 4 * q;
-      if (lane >= k && lane < L && k < L)
-        Db[k * kLd + lane] -= ws[lane] * vs[k] + vs[lane] * ws[k];
-      if (lane < nC && k < L) Cb[k * kLd + lane] -= us[lane] * vs[k];
+      wr[q] = (k >= 1) ? tv * wave_sum(vl * xr[q]) : 0.0;
+      const double cs = wave_sum(lane > k ? vl * xd[q] : 0.0);
+      if (lane == 0) ys2[k] = cs;
+      ry += xd[q] * vk[q];
+      ru += xc[q] * vk[q];
+    }
+    py[wave][lane] = ry;
+    pu[wave][lane] = ru;
+    __syncthreads();
+    // y = D v, u = tau C v, mu = v^T y, w = tau y - tau^2 mu / 2 v (every
+    // wave forms the values of its own rows and columns)
+    const double yl = py[0][lane] + py[1][lane] + py[2][lane] + py[3][lane] + ys2[lane];
+    const double ul = tv * (pu[0][lane] + pu[1][lane] + pu[2][lane] + pu[3][lane]);
+    const double mu = wave_sum(vl * yl);
+    const double h2 = 0.5 * tv * tv * mu;
+    const double wl = tv * yl - h2 * vl;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int k = wave + 4 * q;
+      const double yk = py[0][k] + py[1][k] + py[2][k] + py[3][k] + ys2[k];
+      const double wk = tv * yk - h2 * vk[q];
+      if (k >= 1) xr[q] -= vl * wr[q];
+      xd[q] -= wl * vk[q] + vl * wk;
+      xc[q] -= ul * vk[q];
     }
   }
-  __syncthreads();
   // store R, D (lower), C; the reflector in its slot
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int k = wave + 4 * q;
-    if (lane < L && k < nR) at(r + lane, c0 + k) = Rb[k * kLd + lane];
-    if (lane < L && k < L && lane >= k) at(r + lane, r + k) = Db[k * kLd + lane];
-    if (lane < nC && k < L) at(r + L + lane, r + k) = Cb[k * kLd + lane];
+    if (lane < L && k < nR) at(r + lane, c0 + k) = xr[q];
+    if (lane < L && k < L && lane >= k) at(r + lane, r + k) = xd[q];
+    if (lane < nC && k < L) at(r + L + lane, r + k) = xc[q];
   }
   const int64_t slot = ehh::slot_offset(n, nb, s) + j;
   if (tid < nb) hh[slot * nb + tid] = tid < L ? vs[tid] : 0.0;
   if (tid == 0) tau[slot] = tv;
 }
 
-// The upper triangle of the result (the LDS chase updates only the lower
-// one): A[k-1, k] = e[k-1], zeros above it up to 2 nb rows.
+// The upper triangle of the result (the register chase updates only the
+// lower one): A[k-1, k] = e[k-1], zeros above it up to 2 nb rows.
 __global__ __launch_bounds__(256) void k_upper_out(double* __restrict__ A, int64_t lda,
                                                    int64_t n, int64_t nb,
                                                    const double* __restrict__ e) {
@@ -411,17 +393,17 @@ int run(int64_t n, int64_t nb, E* A, int64_t lda, double* d, double* e, E* hh, E
   // 3 s + J(s) > t (3 s + J(s) increases with s)
   int64_t T = 0;
   for (int64_t s = 0; s <= n - 2; ++s) T = std::max(T, kLag * s + steps_of(n, nb, s));
-  // real bands up to 64 wide take the LDS-staged, lower-triangle steps
+  // real bands up to 64 wide take the register, lower-triangle steps
   constexpr bool real = std::is_same<E, double>::value;
-  const bool lds = real && nb <= 64;
+  const bool lower = real && nb <= 64;
   int64_t s_lo = 0;
   for (int64_t t = 0; t < T; ++t) {
     while (s_lo <= n - 2 && kLag * s_lo + steps_of(n, nb, s_lo) <= t) ++s_lo;
     const int64_t s_hi = std::min<int64_t>(t / kLag, n - 2);
     if (s_hi < s_lo) continue;
     if constexpr (real) {
-      if (lds) {
-        hipLaunchKernelGGL(k_chase_lds, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, st, A,
+      if (lower) {
+        hipLaunchKernelGGL(k_chase_reg, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, st, A,
                            lda, n, nb, t, s_lo, hh, tau);
         continue;
       }
@@ -432,7 +414,7 @@ int run(int64_t n, int64_t nb, E* A, int64_t lda, double* d, double* e, E* hh, E
   const unsigned g = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
   hipLaunchKernelGGL(k_diag_out<E>, dim3(g), dim3(256), 0, st, (const E*)A, lda, n, d, e);
   if constexpr (real) {
-    if (lds && n > 1)
+    if (lower && n > 1)
       hipLaunchKernelGGL(k_upper_out, dim3((unsigned)n - 1), dim3(256), 0, st, (double*)A, lda,
                          n, nb, (const double*)e);
   }
