@@ -252,7 +252,7 @@ def served_stream(args):
                     for q in sample}}}
 
 
-def batched_workload(quick=False, order=0):
+def batched_workload(quick=False, order=0, k=0):
     """The batched workload: 256 real fp64 problems, n_i ~ U{200..2000}
     (seed 401), nbw 32, nev = n_i, all back-transforms in one batched call
     (inputs drawn on the device).  Timed with the library's default plan, then
@@ -285,7 +285,8 @@ def batched_workload(quick=False, order=0):
 
     P.tuner_clear()
     P.profile_enable(True)
-    t_default = timed(lambda: P.hh_trafo_batched(probs, order=order if quick else 0))
+    t_default = timed(lambda: P.hh_trafo_batched(probs, order=order if quick else 0,
+                                                 k=k if quick else 0))
     pr = P.profile_last()
     P.profile_enable(False)
     if quick:
@@ -787,7 +788,8 @@ def main():
         print(json.dumps({"served_stream": served_stream(args)}), flush=True)
         return
     if args.batched_only:
-        print(json.dumps({"batched_workload": batched_workload(quick=True, order=args.order)}),
+        print(json.dumps({"batched_workload": batched_workload(quick=True, order=args.order,
+                                                               k=args.k)}),
               flush=True)
         return
     if args.bt2_only:

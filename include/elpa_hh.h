@@ -319,6 +319,20 @@ int64_t elpa_hh_workspace_bytes_batched(const elpa_hh_problem *probs, int64_t co
 int elpa_hh_plan_supported(int64_t nbw, int32_t dtype, const elpa_hh_plan *plan);
 
 /*
+ * The kernel a call would run for a problem of this size: *out = the plan
+ * (`plan` as given, or the tuner's for the size class where `plan` leaves
+ * the kernel open) with path and k filled in by the library's choice
+ * (path ELPA_PATH_REF and k 0 for the reference kernel).  batched != 0: as a
+ * problem of elpa_hh_trafo_batched (whose choice prefers the kernels with a
+ * one-launch form, and k = 96 at nbw = 32), else as elpa_hh_trafo_plan.
+ * steps, order, streams and batch stay 0 where the library picks them at
+ * launch.  ELPA_ERR_PLAN if `plan` cannot run, ELPA_ERR_ARG / _DTYPE for bad
+ * arguments.  Host only, nothing enqueued.
+ */
+int elpa_hh_chosen_plan(int64_t n, int64_t nev, int64_t nbw, int32_t dtype, int32_t batched,
+                        const elpa_hh_plan *plan, elpa_hh_plan *out);
+
+/*
  * Kernel timing (benchmarks, tests).  While enabled on a host thread, every
  * call made from that thread on the device that was current at enable time
  * records HIP events around its main kernel sequence (the tile launches of

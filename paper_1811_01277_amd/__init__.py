@@ -14,7 +14,7 @@ from .binding import (  # noqa: F401
     R32, R64, ElpaError, band_to_tridiag, bt2_trafo, full_to_band, cholesky_inverse,
     generalized_to_standard, generalized_back, tridiag_eigh, eigenvectors,
     generalized_eigenvectors, bt2_workspace_bytes, hh_trafo,
-    hh_trafo_batched, hh_trafo_batched_ptr, hh_trafo_noalloc_ptr, hh_trafo_ptr, library, library_path, num_reflectors, plan_supported,
+    hh_trafo_batched, hh_trafo_batched_ptr, chosen_plan, hh_trafo_noalloc_ptr, hh_trafo_ptr, library, library_path, num_reflectors, plan_supported,
     profile_enable, profile_last, slot_offset, strerror, version, workspace_bytes,
     workspace_bytes_batched, workspace_cached, workspace_release, tune, tune_batched, tuner_clear, tuner_get, tuner_load, tuner_save, tuner_set,
     tuner_size, NOALLOC_SCRATCH_BYTES,

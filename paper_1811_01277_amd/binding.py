@@ -70,6 +70,9 @@ def library():
         L.elpa_hh_batch_destroy.restype = C.c_int
         L.elpa_hh_trafo_batched.argtypes = [C.POINTER(_Problem), i64, p, C.POINTER(_Plan)]
         L.elpa_hh_trafo_batched.restype = C.c_int
+        L.elpa_hh_chosen_plan.argtypes = [i64, i64, i64, i32, i32, C.POINTER(_Plan),
+                                          C.POINTER(_Plan)]
+        L.elpa_hh_chosen_plan.restype = C.c_int
         L.elpa_hh_plan_supported.argtypes = [i64, i32, C.POINTER(_Plan)]
         L.elpa_hh_plan_supported.restype = C.c_int
         L.elpa_hh_workspace_bytes.argtypes = [i64, i64, i64, i32, C.POINTER(_Plan)]
@@ -243,6 +246,17 @@ def _plan(path, k, steps=0, order=0, streams=0, batch=0):
 def plan_supported(nbw, dtype, path=PATH_AUTO, k=0):
     pl = _plan(path, k)
     return bool(library().elpa_hh_plan_supported(nbw, dtype, C.byref(pl) if pl else None))
+
+
+def chosen_plan(n, nev, nbw, dtype, batched=False, path=None, k=0):
+    """The plan (path, k filled in) a single or batched call runs for this
+    problem size (elpa_hh_chosen_plan)."""
+    pl = _plan(path, k)
+    out = _Plan()
+    _check(library().elpa_hh_chosen_plan(n, nev, nbw, dtype, 1 if batched else 0,
+                                         C.byref(pl) if pl is not None else None,
+                                         C.byref(out)))
+    return _plan_dict(out)
 
 
 def workspace_bytes(n, nev, nbw, dtype, path=None, k=0):

@@ -38,14 +38,22 @@ const ehh::StripeEntry* find_entry(int path, int32_t dtype, int64_t nb, int k) {
 
 // Library default of the sweeps fused per pass, per kernel family: the first
 // compiled entry in order of preference (0 if none).
-int default_k(int path, int32_t dtype, int64_t nb) {
+int default_k(int path, int32_t dtype, int64_t nb, bool batched) {
   static const int split_pref[] = {80, 64, 48, 32, 96, 24, 16};
+  // batched calls at nbw = 32: the widest k that holds its window without
+  // spilling (k = 96 takes the 256-problem batched workload from 42.2 to
+  // 39.4 ms of kernel time against k = 64; a single small problem has too
+  // few sweep blocks for it: n = 512 takes 0.50 instead of 0.43 ms)
+  static const int split_pref32[] = {96, 64, 48, 32};
   static const int wy_pref[] = {160, 128, 96, 64, 48, 32};
   static const int wy_pref32[] = {96, 64, 32, 128};
   static const int wy_pref_c[] = {48, 32, 16};
   static const int stripe_pref[] = {32, 16, 8, 4};
   static const int stripe_pref_c[] = {4, 2};
   if (path == ELPA_PATH_SPLIT) {
+    if (nb == 32 && batched)
+      for (int k : split_pref32)
+        if (find_entry(path, dtype, nb, k)) return k;
     for (int k : split_pref)
       if (find_entry(path, dtype, nb, k)) return k;
     return 0;
@@ -104,7 +112,7 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
     case ELPA_PATH_STRIPE:
     case ELPA_PATH_SPLIT:
     case ELPA_PATH_WY: {
-      const int kk = k ? k : default_k(want, dtype, nb);
+      const int kk = k ? k : default_k(want, dtype, nb, batched);
       const ehh::StripeEntry* e = kk ? find_entry(want, dtype, nb, kk) : nullptr;
       if (!e || (batched && !e->batched)) {
         *rc = ELPA_ERR_PLAN;
@@ -131,7 +139,7 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
       const int nf = dtype == ELPA_R32 ? 3 : 2;
       for (int f = 0; f < nf; ++f) {
         const int fam = fams[f];
-        const int kk = k ? k : default_k(fam, dtype, nb);
+        const int kk = k ? k : default_k(fam, dtype, nb, batched);
         const ehh::StripeEntry* e = kk ? find_entry(fam, dtype, nb, kk) : nullptr;
         if (e && !(batched && !e->batched)) {
           *path = fam;
@@ -295,6 +303,21 @@ int elpa_hh_plan_supported(int64_t nbw, int32_t dtype, const elpa_hh_plan* plan)
   int path = 0, rc = 0;
   (void)resolve(dtype, nbw, plan, &path, &rc);
   return rc == ELPA_OK ? 1 : 0;
+}
+
+int elpa_hh_chosen_plan(int64_t n, int64_t nev, int64_t nbw, int32_t dtype, int32_t batched,
+                        const elpa_hh_plan* plan, elpa_hh_plan* out) {
+  if (!out || n < 0 || nev < 0 || nbw < 1) return ELPA_ERR_ARG;
+  if (elem_size(dtype) == 0) return ELPA_ERR_DTYPE;
+  elpa_hh_plan tuned{};
+  const elpa_hh_plan* pp = effective_plan(dtype, nbw, n, nev, plan, &tuned);
+  int path = 0, rc = 0;
+  const ehh::StripeEntry* se = resolve(dtype, nbw, pp, &path, &rc, batched != 0, n);
+  if (rc != ELPA_OK) return rc;
+  *out = pp ? *pp : elpa_hh_plan{};
+  out->path = path;
+  out->k = se ? se->k : 0;
+  return ELPA_OK;
 }
 
 int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, const void* tau,

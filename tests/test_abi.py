@@ -310,3 +310,25 @@ def test_tridiag_eigh_argument_errors():
     assert lib.elpa_tridiag_eigh(10, 3, nul, nul, nul, nul, 10, P.R64, nul) == -1
     assert lib.elpa_tridiag_eigh(1 << 31, 0, nul, nul, nul, nul, 1 << 31, P.R64, nul) == -1
     assert lib.elpa_tridiag_eigh(0, 0, nul, nul, nul, nul, 1, P.R64, nul) == 0
+
+
+def test_chosen_plan_single_and_batched():
+    """The kernel choice a call would make, without a device: the compact-WY
+    kernel for large fp64 single calls, the two-lane kernel below n = 3000 and
+    in batched calls (k = 96 at nbw = 32 there, 64 for a single call)."""
+    P.tuner_clear()
+    assert P.chosen_plan(20000, 20000, 64, P.R64)["path"] == P.PATH_WY
+    assert P.chosen_plan(20000, 20000, 64, P.R64)["k"] == 160
+    one = P.chosen_plan(1000, 1000, 64, P.R64)
+    assert one["path"] == P.PATH_SPLIT and one["k"] == 80
+    assert P.chosen_plan(20000, 20000, 64, P.R64, batched=True)["path"] == P.PATH_SPLIT
+    assert P.chosen_plan(1000, 1000, 32, P.R64)["k"] == 64
+    assert P.chosen_plan(1000, 1000, 32, P.R64, batched=True)["k"] == 96
+    assert P.chosen_plan(1000, 1000, 32, P.R64, path=P.PATH_SPLIT, k=32)["k"] == 32
+    assert P.chosen_plan(100, 100, 7, P.R64)["path"] == P.PATH_REF
+    with pytest.raises(P.ElpaError) as e:
+        P.chosen_plan(100, 100, 64, P.R64, path=P.PATH_SPLIT, k=63)
+    assert e.value.code == -6
+    with pytest.raises(P.ElpaError) as e:
+        P.chosen_plan(100, 100, 64, 9)
+    assert e.value.code == -2

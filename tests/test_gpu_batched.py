@@ -16,6 +16,15 @@ from oracle import bt, checks
 
 pytestmark = pytest.mark.gpu
 
+
+def batched_k(q, nbw, path=None):
+    """k of the kernel a batched call runs for this problem (the batched
+    choice can differ from a single call's: k = 96 at nbw = 32)."""
+    import paper_1811_01277_amd as P
+    from paper_1811_01277_amd import binding as B
+    n, nev = q.shape
+    return P.chosen_plan(n, nev, nbw, B._dtype_code(q), batched=True, path=path)["k"]
+
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
 
 
@@ -70,7 +79,8 @@ def test_batch_matches_oracle_and_single_calls(torch_dev, sched):
     for (q, h, t, nbw) in probs:
         qq = q.clone()  # new storage, same column-major strides
         assert qq.data_ptr() != q.data_ptr() and qq.stride() == q.stride()
-        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT)   # the kernel batched calls run
+        # the kernel batched calls run
+        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT, k=batched_k(q, nbw))
         singles.append(qq)
     print("batch of", len(probs), "problems", flush=True)
     P.profile_enable(True)
@@ -110,7 +120,7 @@ def test_fp32_batch_equals_single_calls(torch_dev, family):
     singles = []
     for (q, h, t, nbw) in probs:
         qq = q.clone()
-        P.hh_trafo(qq, h, t, nbw, path=path)
+        P.hh_trafo(qq, h, t, nbw, path=path, k=batched_k(q, nbw, path))
         singles.append(qq)
     P.profile_enable(True)
     try:
@@ -184,7 +194,7 @@ def test_batched_workload_sampled(torch_dev):
     for i in check:
         q, h, t, nbw = probs[i]
         qq = q.clone()
-        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT)
+        P.hh_trafo(qq, h, t, nbw, path=P.PATH_SPLIT, k=batched_k(q, nbw))
         singles[i] = qq
     print("batched workload: 256 problems", flush=True)
     P.profile_enable(True)
