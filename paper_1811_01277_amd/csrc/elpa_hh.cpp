@@ -81,12 +81,16 @@ int default_k(int path, int32_t dtype, int64_t nb, bool batched) {
 // fp64 from n = 3000 on (k = 128, from n = 6000 k = 160: a larger k reuses
 // every loaded row more but leaves fewer sweep blocks to run side by side);
 // 0 = the two-lane VALU kernel (fp64 below n = 3000, other nbw, batched
-// calls).
-int auto_wy_k(int32_t dtype, int64_t nb, int64_t n) {
+// calls).  fp64 with fewer than 1024 columns also takes the two-lane kernel:
+// the compact-WY kernel's T-build, which does not shrink with nev, is then a
+// large part of the call (n = 8192, nev = 819: 6.7 ms two-lane, 7.9 ms WY;
+// nev = 2000 at n = 20000 is faster on WY).  nev = 0: not known, taken as
+// large.
+int auto_wy_k(int32_t dtype, int64_t nb, int64_t n, int64_t nev) {
   if (nb != 64) return 0;
   if (dtype == ELPA_R32) return 96;
   if (dtype == ELPA_C64) return 48;
-  if (dtype == ELPA_R64 && n >= 3000) return n >= 6000 ? 160 : 128;
+  if (dtype == ELPA_R64 && n >= 3000 && (nev == 0 || nev >= 1024)) return n >= 6000 ? 160 : 128;
   return 0;
 }
 
@@ -96,7 +100,7 @@ int auto_wy_k(int32_t dtype, int64_t nb, int64_t n) {
 // batched: the kernel must have a batched form, and the library choice
 // prefers the two-lane kernel (its one-launch batched schedule).
 const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* plan, int* path,
-                                int* rc, bool batched = false, int64_t n = 0) {
+                                int* rc, bool batched = false, int64_t n = 0, int64_t nev = 0) {
   *rc = ELPA_OK;
   if (plan && (plan->order < ELPA_ORDER_AUTO || plan->order > ELPA_ORDER_XCD ||
                plan->streams < 0 || plan->streams > 8 || plan->batch < ELPA_BATCH_AUTO ||
@@ -123,7 +127,7 @@ const ehh::StripeEntry* resolve(int32_t dtype, int64_t nb, const elpa_hh_plan* p
     }
     case ELPA_PATH_AUTO: {
       if (!batched && k == 0) {
-        const int wk = auto_wy_k(dtype, nb, n);
+        const int wk = auto_wy_k(dtype, nb, n, nev);
         const ehh::StripeEntry* e = wk ? find_entry(ELPA_PATH_WY, dtype, nb, wk) : nullptr;
         if (e) {
           *path = ELPA_PATH_WY;
@@ -312,7 +316,7 @@ int elpa_hh_chosen_plan(int64_t n, int64_t nev, int64_t nbw, int32_t dtype, int3
   elpa_hh_plan tuned{};
   const elpa_hh_plan* pp = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0, rc = 0;
-  const ehh::StripeEntry* se = resolve(dtype, nbw, pp, &path, &rc, batched != 0, n);
+  const ehh::StripeEntry* se = resolve(dtype, nbw, pp, &path, &rc, batched != 0, n, nev);
   if (rc != ELPA_OK) return rc;
   *out = pp ? *pp : elpa_hh_plan{};
   out->path = path;
@@ -328,7 +332,7 @@ int elpa_hh_trafo_plan(int64_t n, int64_t nev, int64_t nbw, const void* hh, cons
   elpa_hh_plan tuned{};
   plan = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0;
-  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc, false, n);
+  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc, false, n, nev);
   if (rc != ELPA_OK) return rc;
   if (n <= 1 || nev == 0) return ELPA_OK;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
@@ -426,7 +430,7 @@ int elpa_hh_batch_create(const elpa_hh_problem* probs, int64_t count, const elpa
     elpa_hh_plan tuned{};
     const elpa_hh_plan* pp = effective_plan(p.dtype, p.nbw, p.n, p.nev, plan, &tuned);
     int path = 0, rc = 0;
-    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, pp, &path, &rc, false, p.n);
+    const ehh::StripeEntry* se = resolve(p.dtype, p.nbw, pp, &path, &rc, false, p.n, p.nev);
     if (rc != ELPA_OK) return rc;
     // every problem's plan must resolve, as in the batched call
     for (int64_t i = 0; i < count; ++i) {
@@ -569,7 +573,7 @@ int64_t elpa_hh_workspace_bytes(int64_t n, int64_t nev, int64_t nbw, int32_t dty
   elpa_hh_plan tuned{};
   plan = effective_plan(dtype, nbw, n, nev, plan, &tuned);
   int path = 0, rc = 0;
-  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc, false, n);
+  const ehh::StripeEntry* se = resolve(dtype, nbw, plan, &path, &rc, false, n, nev);
   if (rc != ELPA_OK) return -1;
   if (n <= 1 || nev == 0 || !se) return 0;
   return (int64_t)se->workspace(n, nev);

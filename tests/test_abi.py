@@ -319,6 +319,10 @@ def test_chosen_plan_single_and_batched():
     P.tuner_clear()
     assert P.chosen_plan(20000, 20000, 64, P.R64)["path"] == P.PATH_WY
     assert P.chosen_plan(20000, 20000, 64, P.R64)["k"] == 160
+    # few columns: the T-build would dominate, the two-lane kernel runs
+    assert P.chosen_plan(8192, 819, 64, P.R64)["path"] == P.PATH_SPLIT
+    assert P.chosen_plan(8192, 1024, 64, P.R64)["path"] == P.PATH_WY
+    assert P.chosen_plan(8192, 819, 64, P.R32)["path"] == P.PATH_WY
     one = P.chosen_plan(1000, 1000, 64, P.R64)
     assert one["path"] == P.PATH_SPLIT and one["k"] == 80
     assert P.chosen_plan(20000, 20000, 64, P.R64, batched=True)["path"] == P.PATH_SPLIT
