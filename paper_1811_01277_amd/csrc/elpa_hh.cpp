@@ -77,9 +77,11 @@ int default_k(int path, int32_t dtype, int64_t nb, bool batched) {
 
 // Library choice for a single problem of size n with semi-bandwidth 64, from
 // sweeps over n = 1000 .. 20000 (nev = n) on this GPU: the compact-WY MFMA
-// kernel for fp32 (k = 96) and complex fp64 (k = 48) at every size, and for
-// fp64 from n = 3000 on (k = 128, from n = 6000 k = 160: a larger k reuses
-// every loaded row more but leaves fewer sweep blocks to run side by side);
+// kernel for fp32 (k = 96, from n = 6000 k = 160) and complex fp64 (k = 48)
+// at every size, and for fp64 from n = 3000 on (k = 128, from n = 6000
+// k = 160): a larger k reuses every loaded row more but leaves fewer sweep
+// blocks to run side by side (fp32 at n = 20000: 82.2 TFLOP/s at k = 160,
+// 77.3 at 96; at n = 4000: 36.9 against 39.2);
 // 0 = the two-lane VALU kernel (fp64 below n = 3000, other nbw, batched
 // calls).  fp64 with fewer than 1024 columns also takes the two-lane kernel:
 // the compact-WY kernel's T-build, which does not shrink with nev, is then a
@@ -88,7 +90,7 @@ int default_k(int path, int32_t dtype, int64_t nb, bool batched) {
 // large.
 int auto_wy_k(int32_t dtype, int64_t nb, int64_t n, int64_t nev) {
   if (nb != 64) return 0;
-  if (dtype == ELPA_R32) return 96;
+  if (dtype == ELPA_R32) return n >= 6000 ? 160 : 96;
   if (dtype == ELPA_C64) return 48;
   if (dtype == ELPA_R64 && n >= 3000 && (nev == 0 || nev >= 1024)) return n >= 6000 ? 160 : 128;
   return 0;

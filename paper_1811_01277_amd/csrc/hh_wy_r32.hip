@@ -13,6 +13,7 @@ const StripeEntry* wy_table_r32(int* size) {
   static const StripeEntry table[] = {
       EHH_WY(float, 1, 64, 64, 2, 2, true, false), EHH_WY(float, 1, 64, 96, 2, 1, true, true),
       EHH_WY(float, 1, 64, 128, 2, 1, true, true), EHH_WY(float, 1, 64, 32, 2, 2, true, false),
+      EHH_WY(float, 1, 64, 160, 2, 1, true, true), EHH_WY(float, 1, 64, 192, 2, 1, true, true),
       EHH_WY(float, 1, 32, 64, 4, 1, true, true), EHH_WY(float, 1, 32, 96, 2, 1, true, true),
   };
   *size = (int)(sizeof(table) / sizeof(table[0]));

@@ -323,6 +323,8 @@ def test_chosen_plan_single_and_batched():
     assert P.chosen_plan(8192, 819, 64, P.R64)["path"] == P.PATH_SPLIT
     assert P.chosen_plan(8192, 1024, 64, P.R64)["path"] == P.PATH_WY
     assert P.chosen_plan(8192, 819, 64, P.R32)["path"] == P.PATH_WY
+    assert P.chosen_plan(20000, 20000, 64, P.R32)["k"] == 160
+    assert P.chosen_plan(4000, 4000, 64, P.R32)["k"] == 96
     one = P.chosen_plan(1000, 1000, 64, P.R64)
     assert one["path"] == P.PATH_SPLIT and one["k"] == 80
     assert P.chosen_plan(20000, 20000, 64, P.R64, batched=True)["path"] == P.PATH_SPLIT

@@ -21,7 +21,7 @@ pytestmark = pytest.mark.gpu
 TOL = {"r64": 1e-12, "c64": 1e-12, "r32": 5e-5}
 KS = [1, 2, 4, 6, 8, 16, 24, 32, 40, 48, 64]
 SPLIT_KS = [16, 24, 32, 48, 64, 80, 96, 128]
-WY_KS = [16, 32, 48, 64, 96, 112, 128, 144, 160]
+WY_KS = [16, 32, 48, 64, 96, 112, 128, 144, 160, 192]
 
 
 @pytest.fixture(scope="module")
