@@ -145,27 +145,39 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
   __shared__ double Gr[16][17], Gi[16][17];
   __shared__ double Tr[16][17], Ti[16][17];
   __shared__ double tr_[16], ti_[16];
+  __shared__ int64_t slot_[16];  // slot of reflector i, -1 if it does not exist
+  __shared__ int len_[16];       // its length L
   const int64_t s0 = m * K;
   if (j >= block_steps(n, NB, K, m)) return;  // no such step
   const int tid = threadIdx.x;
   const int64_t mb = block_base(n, NB, K, m);
   if (j == 0 && u == 0 && tid == 0) Bt[m] = mb;
-  const int64_t ctot = csum(n - 1, NB);
-  for (int e = tid; e < RP * 16; e += 256) {
-    const int rho = e / 16, i = e % 16;
-    const int64_t s = s0 + 16 * u + i;
-    double vr = 0.0, vi = 0.0;
+  if (tid < 16) {  // the sub-group's 16 slots, once (integer divisions)
+    const int64_t s = s0 + 16 * u + tid;
+    int64_t slot = -1;
+    int L = 0;
     if (s <= n - 2 && j < (n - 1 - s + NB - 1) / NB) {
-      const int64_t slot = ctot - csum(n - 1 - s, NB) + j;
+      slot = csum(n - 1, NB) - csum(n - 1 - s, NB) + j;
       const int64_t r = s + 1 + j * NB;
-      const int64_t L = (NB < n - r) ? NB : n - r;
-      const int d = rho - i;
-      if (d >= 0 && d < L) wy_get<E>(hh[slot * NB + d], vr, vi);
-      if (rho == 0) wy_get<E>(tau[slot], tr_[i], ti_[i]);
-    } else if (rho == 0) {
-      tr_[i] = 0.0;
-      ti_[i] = 0.0;
+      L = (int)((NB < n - r) ? NB : n - r);
     }
+    slot_[tid] = slot;
+    len_[tid] = L;
+    if (slot >= 0) {
+      wy_get<E>(tau[slot], tr_[tid], ti_[tid]);
+    } else {
+      tr_[tid] = 0.0;
+      ti_[tid] = 0.0;
+    }
+  }
+  __syncthreads();
+  // consecutive threads take consecutive entries of one slot (coalesced)
+  for (int e = tid; e < RP * 16; e += 256) {
+    const int i = e / RP, rho = e % RP;
+    const int64_t slot = slot_[i];
+    const int d = rho - i;
+    double vr = 0.0, vi = 0.0;
+    if (slot >= 0 && d >= 0 && d < len_[i]) wy_get<E>(hh[slot * NB + d], vr, vi);
     Vr[rho][i] = vr;
     Vi[rho][i] = vi;
   }
@@ -184,14 +196,13 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
     Ti[a][b] = 0.0;
   }
   __syncthreads();
+  // forward recurrence, column i: T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i].
+  // Entry (a, i) needs only row a of T (T[a][l] = 0 for l < a), so lane a
+  // computes its whole row in column order, with no barrier in between.
   if (tid < 16) {
     Tr[tid][tid] = tr_[tid];
     Ti[tid][tid] = ti_[tid];
-  }
-  __syncthreads();
-  // forward recurrence, column i: T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-  for (int i = 1; i < 16; ++i) {
-    if (tid < i) {
+    for (int i = tid + 1; i < 16; ++i) {
       double ar = 0.0, ai = 0.0;
       for (int l = tid; l < i; ++l) {
         ar += Tr[tid][l] * Gr[l][i] - Ti[tid][l] * Gi[l][i];
@@ -200,8 +211,8 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
       Tr[tid][i] = -(tr_[i] * ar - ti_[i] * ai);
       Ti[tid][i] = -(tr_[i] * ai + ti_[i] * ar);
     }
-    __syncthreads();
   }
+  __syncthreads();
   R* __restrict__ rec = P + ((mb + j) * Gm::SG + u) * (int64_t)WyRec<E, NB, K>::REC;
   for (int e = tid; e < NF * 64; e += 256) {
     const int f = e / 64, lane = e % 64;
