@@ -100,3 +100,35 @@ def test_cache_accounting_and_release(torch_dev):
     torch.cuda.synchronize()
     freed = P.workspace_release()
     assert freed >= one - base and P.workspace_cached() == 0
+
+
+def test_cache_evicts_idle_blocks_beyond_its_bound(torch_dev):
+    """Idle blocks beyond 8 GiB are freed, least recently used first, before a
+    new block is allocated: a large call's block (n = nev = 20000) is evicted
+    when a smaller call that cannot reuse it (less than half its size) would
+    take the idle total past the bound."""
+    torch, dev = torch_dev
+    import paper_1811_01277_amd as P
+    bound = 8 << 30
+    na, nb_ = 20000, 12000
+    wa = P.workspace_bytes(na, na, 64, P.R64)
+    wb = P.workspace_bytes(nb_, nb_, 64, P.R64)
+    assert wb < wa // 2 and wa > bound - wb, (wa, wb)   # the case this test needs
+    torch.cuda.synchronize()
+    P.workspace_release()
+    g = torch.Generator(device=dev)
+    g.manual_seed(3200)
+    print(f"eviction: workspaces {wa / 1e9:.2f} and {wb / 1e9:.2f} GB", flush=True)
+    for n in (na, nb_):
+        hh, tau = W.device_reflectors(torch, n, 64, dev, g)
+        q = W.device_block(torch, n, n, dev, g)
+        P.hh_trafo(q, hh, tau, 64)
+        torch.cuda.synchronize()
+        held = P.workspace_cached()
+        if n == na:
+            assert held >= wa
+        else:
+            assert wb <= held < wa, held       # the large block was freed
+        del hh, tau, q
+    P.workspace_release()
+    assert P.workspace_cached() == 0
