@@ -82,19 +82,25 @@ int default_k(int path, int32_t dtype, int64_t nb, bool batched) {
 // k = 160): a larger k reuses every loaded row more but leaves fewer sweep
 // blocks to run side by side (fp32 at n = 20000: 82.2 TFLOP/s at k = 160,
 // 77.3 at 96; at n = 4000: 36.9 against 39.2);
-// 0 = the two-lane VALU kernel (fp64 below n = 3000, fp32 and complex at
-// nbw = 32, other nbw, batched calls).  fp64 with fewer than 1024 columns
+// 0 = the two-lane VALU kernel (fp64 below n = 3000, complex at nbw = 32,
+// other nbw, batched calls).  fp64 with fewer than 1024 columns
 // also takes the two-lane kernel:
 // the compact-WY kernel's T-build, which does not shrink with nev, is then a
 // large part of the call (n = 8192, nev = 819: 6.7 ms two-lane, 7.9 ms WY;
 // nev = 2000 at n = 20000 is faster on WY).  nev = 0: not known, taken as
 // large.
 int auto_wy_k(int32_t dtype, int64_t nb, int64_t n, int64_t nev) {
-  // nbw = 32, fp64: the compact-WY kernel from n = 2000 despite its 1.5x
-  // executed flops there (n = 2000 / 4000 / 6000 / 12000: 8.0 / 21.7 / 29.2
-  // / 34.3 TFLOP/s against 6.1 / 17.1 / 25.1 / 31.7 for the two-lane kernel)
+  // nbw = 32, real: the compact-WY kernel from n = 2000 despite its 1.5x
+  // executed flops there (fp64, n = 2000 / 4000 / 6000 / 12000: 8.0 / 21.7 /
+  // 29.2 / 34.3 TFLOP/s against 6.1 / 17.1 / 25.1 / 31.7 for the two-lane
+  // kernel; fp32 at n = 2000 / 6000 / 12000: 10.6 / 44.3 / 54.4 against 7.3 /
+  // 36.8 / 52.6); complex keeps the two-lane kernel (n = 6000: 37.5 against
+  // 31.4 for WY k = 32)
   if (nb == 32)
-    return (dtype == ELPA_R64 && n >= 2000 && (nev == 0 || nev >= 1024)) ? 96 : 0;
+    return ((dtype == ELPA_R64 || dtype == ELPA_R32) && n >= 2000 &&
+            (nev == 0 || nev >= 1024))
+               ? 96
+               : 0;
   if (nb != 64) return 0;
   if (dtype == ELPA_R32) return n >= 6000 ? 160 : 96;
   if (dtype == ELPA_C64) return 48;

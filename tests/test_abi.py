@@ -331,6 +331,8 @@ def test_chosen_plan_single_and_batched():
     assert P.chosen_plan(1000, 1000, 32, P.R64)["k"] == 64
     big32 = P.chosen_plan(4000, 4000, 32, P.R64)
     assert big32["path"] == P.PATH_WY and big32["k"] == 96
+    assert P.chosen_plan(4000, 4000, 32, P.R32)["path"] == P.PATH_WY
+    assert P.chosen_plan(4000, 4000, 32, P.C64)["path"] == P.PATH_SPLIT
     assert P.chosen_plan(1000, 1000, 32, P.R64, batched=True)["k"] == 96
     assert P.chosen_plan(1000, 1000, 32, P.R64, path=P.PATH_SPLIT, k=32)["k"] == 32
     assert P.chosen_plan(100, 100, 7, P.R64)["path"] == P.PATH_REF
