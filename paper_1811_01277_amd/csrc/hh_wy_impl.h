@@ -147,12 +147,18 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
   __shared__ double tr_[16], ti_[16];
   __shared__ int64_t slot_[16];  // slot of reflector i, -1 if it does not exist
   __shared__ int len_[16];       // its length L
+  __shared__ int64_t mb_;        // the block's first step record
   const int64_t s0 = m * K;
   if (j >= block_steps(n, NB, K, m)) return;  // no such step
   const int tid = threadIdx.x;
-  const int64_t mb = block_base(n, NB, K, m);
-  if (j == 0 && u == 0 && tid == 0) Bt[m] = mb;
-  if (tid < 16) {  // the sub-group's 16 slots, once (integer divisions)
+  // 64-bit integer divisions are emulated in many instructions: the block
+  // base (a floor sum) and the slots are computed once, by one and sixteen
+  // threads, not by every thread
+  if (tid == 64) {
+    mb_ = block_base(n, NB, K, m);
+    if (j == 0 && u == 0) Bt[m] = mb_;
+  }
+  if (tid < 16) {  // the sub-group's 16 slots, once
     const int64_t s = s0 + 16 * u + tid;
     int64_t slot = -1;
     int L = 0;
@@ -182,13 +188,18 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
     Vi[rho][i] = vi;
   }
   __syncthreads();
+  // (real data: the imaginary parts are zero and their terms are skipped)
   {  // Gram matrix G = V^H V
     const int a = tid / 16, b = tid % 16;
     double gr = 0.0, gi = 0.0;
     for (int rho = 0; rho < RP; ++rho) {
       // conj(V[rho][a]) V[rho][b]
-      gr += Vr[rho][a] * Vr[rho][b] + Vi[rho][a] * Vi[rho][b];
-      gi += Vr[rho][a] * Vi[rho][b] - Vi[rho][a] * Vr[rho][b];
+      if constexpr (CPLX) {
+        gr += Vr[rho][a] * Vr[rho][b] + Vi[rho][a] * Vi[rho][b];
+        gi += Vr[rho][a] * Vi[rho][b] - Vi[rho][a] * Vr[rho][b];
+      } else {
+        gr += Vr[rho][a] * Vr[rho][b];
+      }
     }
     Gr[a][b] = gr;
     Gi[a][b] = gi;
@@ -205,15 +216,23 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
     for (int i = tid + 1; i < 16; ++i) {
       double ar = 0.0, ai = 0.0;
       for (int l = tid; l < i; ++l) {
-        ar += Tr[tid][l] * Gr[l][i] - Ti[tid][l] * Gi[l][i];
-        ai += Tr[tid][l] * Gi[l][i] + Ti[tid][l] * Gr[l][i];
+        if constexpr (CPLX) {
+          ar += Tr[tid][l] * Gr[l][i] - Ti[tid][l] * Gi[l][i];
+          ai += Tr[tid][l] * Gi[l][i] + Ti[tid][l] * Gr[l][i];
+        } else {
+          ar += Tr[tid][l] * Gr[l][i];
+        }
       }
-      Tr[tid][i] = -(tr_[i] * ar - ti_[i] * ai);
-      Ti[tid][i] = -(tr_[i] * ai + ti_[i] * ar);
+      if constexpr (CPLX) {
+        Tr[tid][i] = -(tr_[i] * ar - ti_[i] * ai);
+        Ti[tid][i] = -(tr_[i] * ai + ti_[i] * ar);
+      } else {
+        Tr[tid][i] = -(tr_[i] * ar);
+      }
     }
   }
   __syncthreads();
-  R* __restrict__ rec = P + ((mb + j) * Gm::SG + u) * (int64_t)WyRec<E, NB, K>::REC;
+  R* __restrict__ rec = P + ((mb_ + j) * Gm::SG + u) * (int64_t)WyRec<E, NB, K>::REC;
   for (int e = tid; e < NF * 64; e += 256) {
     const int f = e / 64, lane = e % 64;
     const int rt = f / 4, kk = f % 4;
@@ -224,8 +243,12 @@ __device__ __forceinline__ void wy_prep_group(const E* __restrict__ hh, const E*
     const int rho = 16 * rt + k;
     double ur = 0.0, ui = 0.0;
     for (int l = c; l < 16; ++l) {
-      ur += Vr[rho][l] * Tr[c][l] + Vi[rho][l] * Ti[c][l];
-      ui += Vi[rho][l] * Tr[c][l] - Vr[rho][l] * Ti[c][l];
+      if constexpr (CPLX) {
+        ur += Vr[rho][l] * Tr[c][l] + Vi[rho][l] * Ti[c][l];
+        ui += Vi[rho][l] * Tr[c][l] - Vr[rho][l] * Ti[c][l];
+      } else {
+        ur += Vr[rho][l] * Tr[c][l];
+      }
     }
     rec[(0 * NF + f) * 64 + lane] = (R)(-ur);
     if constexpr (CPLX) rec[(1 * NF + f) * 64 + lane] = (R)ui;
