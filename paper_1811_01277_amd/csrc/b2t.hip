@@ -256,18 +256,22 @@ __global__ __launch_bounds__(512) void k_chase(E* __restrict__ A, int64_t lda, i
 //   D = rows and columns [r, r+L)         <- H D H (symmetric; with y = D v,
 //       mu = v^T y and w = tau y - tau^2 mu / 2 v: D <- D - w v^T - v w^T)
 //   C = rows [r+L, hi) x columns [r, r+L) <- C H   (hi = min(r+L+nb, n))
-// Lane i of every wave holds row i of each block, wave w the columns w, w+4,
-// ..., so each block is one coalesced load per column, all issued before any
-// value is used, and one store.  Column sums (v^T R, the strictly-lower part
-// of D^T v) are wave reductions; row sums (the lower part of D v, C v) add
-// the four waves' partial sums through LDS.  Two barriers per step.  The
+// Lane i of every wave holds row i of each block, wave w of the NW waves the
+// columns w, w+NW, ..., so each block is one coalesced load per column, all
+// issued before any value is used, and one store.  Column sums (v^T R, the
+// strictly-lower part of D^T v) are wave reductions; row sums (the lower part
+// of D v, C v) add the waves' partial sums through LDS.  Two barriers per
+// step.  With eight waves each wave's chain of column reductions is half as
+// long as with four (n = 20000, nbw = 64: 0.80 s against 1.04 s; sixteen
+// waves gave 0.81 s).  The
 // lower-triangle entries the steps touch are a subset of the two-sided form's,
 // so the launch schedule's disjointness holds unchanged.
-__global__ __launch_bounds__(256) void k_chase_reg(double* __restrict__ A, int64_t lda, int64_t n,
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void k_chase_reg(double* __restrict__ A, int64_t lda, int64_t n,
                                                    int64_t nb, int64_t t, int64_t s_lo,
                                                    double* __restrict__ hh,
                                                    double* __restrict__ tau) {
-  __shared__ double vs[64], ys2[64], py[4][64], pu[4][64];
+  __shared__ double vs[64], ys2[64], py[NW][64], pu[NW][64];
   __shared__ double sh_tau;
   const int64_t s = s_lo + blockIdx.x;
   const int64_t j = t - kLag * s;
@@ -279,10 +283,11 @@ __global__ __launch_bounds__(256) void k_chase_reg(double* __restrict__ A, int64
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   auto at = [&](int64_t i, int64_t k) -> double& { return A[i + k * lda]; };
 
-  double xr[16], xd[16], xc[16];
+  constexpr int NQ = 64 / NW;  // columns per wave
+  double xr[NQ], xd[NQ], xc[NQ];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int k = wave + 4 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int k = wave + NW * q;
     xr[q] = (lane < L && k < nR) ? at(r + lane, c0 + k) : 0.0;
     xd[q] = (lane < L && k < L && lane >= k) ? at(r + lane, r + k) : 0.0;
     xc[q] = (lane < nC && k < L) ? at(r + L + lane, r + k) : 0.0;
@@ -307,17 +312,17 @@ __global__ __launch_bounds__(256) void k_chase_reg(double* __restrict__ A, int64
   __syncthreads();
   const double tv = sh_tau;
   const double vl = vs[lane];
-  double vk[16];
+  double vk[NQ];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) vk[q] = vs[wave + 4 * q];
+  for (int q = 0; q < NQ; ++q) vk[q] = vs[wave + NW * q];
   if (tv != 0.0) {
     // column sums: v^T R (R's update) and the strictly lower part of D^T v;
     // row sums: the lower part of D v and C v, per wave
-    double wr[16];
+    double wr[NQ];
     double ry = 0.0, ru = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = wave + 4 * q;
+    for (int q = 0; q < NQ; ++q) {
+      const int k = wave + NW * q;
       wr[q] = (k >= 1) ? tv * wave_sum(vl * xr[q]) : 0.0;
       const double cs = wave_sum(lane > k ? vl * xd[q] : 0.0);
       if (lane == 0) ys2[k] = cs;
@@ -329,15 +334,22 @@ __global__ __launch_bounds__(256) void k_chase_reg(double* __restrict__ A, int64
     __syncthreads();
     // y = D v, u = tau C v, mu = v^T y, w = tau y - tau^2 mu / 2 v (every
     // wave forms the values of its own rows and columns)
-    const double yl = py[0][lane] + py[1][lane] + py[2][lane] + py[3][lane] + ys2[lane];
-    const double ul = tv * (pu[0][lane] + pu[1][lane] + pu[2][lane] + pu[3][lane]);
+    double yl = ys2[lane], us = 0.0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      yl += py[w][lane];
+      us += pu[w][lane];
+    }
+    const double ul = tv * us;
     const double mu = wave_sum(vl * yl);
     const double h2 = 0.5 * tv * tv * mu;
     const double wl = tv * yl - h2 * vl;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int k = wave + 4 * q;
-      const double yk = py[0][k] + py[1][k] + py[2][k] + py[3][k] + ys2[k];
+    for (int q = 0; q < NQ; ++q) {
+      const int k = wave + NW * q;
+      double yk = ys2[k];
+#pragma unroll
+      for (int w = 0; w < NW; ++w) yk += py[w][k];
       const double wk = tv * yk - h2 * vk[q];
       if (k >= 1) xr[q] -= vl * wr[q];
       xd[q] -= wl * vk[q] + vl * wk;
@@ -346,8 +358,8 @@ __global__ __launch_bounds__(256) void k_chase_reg(double* __restrict__ A, int64
   }
   // store R, D (lower), C; the reflector in its slot
 #pragma unroll
-  for (int q = 0; q < 16; ++q) {
-    const int k = wave + 4 * q;
+  for (int q = 0; q < NQ; ++q) {
+    const int k = wave + NW * q;
     if (lane < L && k < nR) at(r + lane, c0 + k) = xr[q];
     if (lane < L && k < L && lane >= k) at(r + lane, r + k) = xd[q];
     if (lane < nC && k < L) at(r + L + lane, r + k) = xc[q];
@@ -403,7 +415,7 @@ int run(int64_t n, int64_t nb, E* A, int64_t lda, double* d, double* e, E* hh, E
     if (s_hi < s_lo) continue;
     if constexpr (real) {
       if (lower) {
-        hipLaunchKernelGGL(k_chase_reg, dim3((unsigned)(s_hi - s_lo + 1)), dim3(256), 0, st, A,
+        hipLaunchKernelGGL(k_chase_reg<8>, dim3((unsigned)(s_hi - s_lo + 1)), dim3(512), 0, st, A,
                            lda, n, nb, t, s_lo, hh, tau);
         continue;
       }
