@@ -154,11 +154,20 @@ __global__ __launch_bounds__(kRows) void k_reflect(const E* __restrict__ A, int6
   // four waves' sums are added in a fixed order
   const E cv = conj_(v);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  for (int64_t j = i + 1; j < b; ++j) {
-    const E x = (row < m && row >= i) ? Num<E>::mul(cv, A[r0 + row + (p + j) * lda])
-                                      : from_re<E>(0.0);
-    const E t = wave_sum(x);
-    if (lane == 0) wred[wave][j] = t;
+  const bool own = row < m && row >= i;
+  // eight columns' values loaded before any is reduced, so their loads are
+  // in flight together
+  constexpr int CH = 8;
+  for (int64_t j0 = i + 1; j0 < b; j0 += CH) {
+    E x[CH];
+#pragma unroll
+    for (int u = 0; u < CH; ++u)
+      x[u] = (own && j0 + u < b) ? A[r0 + row + (p + j0 + u) * lda] : from_re<E>(0.0);
+#pragma unroll
+    for (int u = 0; u < CH; ++u) {
+      const E t = wave_sum(Num<E>::mul(cv, x[u]));
+      if (lane == 0 && j0 + u < b) wred[wave][j0 + u] = t;
+    }
   }
   __syncthreads();
   for (int64_t j = i + 1 + threadIdx.x; j < b; j += blockDim.x) {
