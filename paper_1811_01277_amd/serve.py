@@ -64,7 +64,7 @@ from dataclasses import dataclass
 
 from . import binding as B
 
-__all__ = ["Request", "Server", "run_plain", "latency_stats"]
+__all__ = ["Request", "Server", "run_plain", "latency_stats", "take_batch"]
 
 
 @dataclass
@@ -102,6 +102,30 @@ def footprint(r):
         r._fp = max(0, B.workspace_bytes(n, nev, r.nbw, dt),
                     B.workspace_bytes_batched([(n, nev, r.nbw, dt)]))
     return r._fp
+
+
+def take_batch(ready, cap, in_use, budget, batch_flops, size=None):
+    """The next batch for a free slot: ready requests, oldest first, while the
+    batch holds fewer than `cap`, its counted flops stay within batch_flops
+    (the first request always goes) and the in-flight workspace stays within
+    `budget` (an idle device, in_use == 0, always takes the oldest request).
+    size(r): workspace bytes of a request (default: footprint).  Returns
+    (batch, its bytes, the requests left, in order)."""
+    size = size or footprint
+    batch, nbytes, work, rest = [], 0, 0.0, []
+    for r in ready:
+        # (conservative for a request that replays its graph, whose workspace
+        # is resident: it may still join a batched call)
+        f = size(r)
+        fits = in_use + nbytes + f <= budget
+        small = not batch or work + r.flops() <= batch_flops
+        if len(batch) < cap and small and (fits or (in_use == 0 and not batch)):
+            batch.append(r)
+            nbytes += f
+            work += r.flops()
+        else:
+            rest.append(r)
+    return batch, nbytes, rest
 
 
 class _Clock:
@@ -236,23 +260,10 @@ class Server:
                 # them, while one on a slot of its own overlaps with them
                 free = sum(x is None for x in busy)
                 cap = min(self.max_batch, -(-len(ready) // free))
-                batch, nbytes, work, rest = [], 0, 0.0, []
-                for r in ready:
-                    # (conservative for a request that replays its graph, whose
-                    # workspace is resident: it may still join a batched call)
-                    f = footprint(r)
-                    fits = in_use + nbytes + f <= self.budget
-                    small = not batch or work + r.flops() <= self.batch_flops
-                    # an idle device always takes the oldest request
-                    if len(batch) < cap and small and (fits or (in_use == 0 and not batch)):
-                        batch.append(r)
-                        nbytes += f
-                        work += r.flops()
-                    else:
-                        rest.append(r)
+                batch, nbytes, ready = take_batch(ready, cap, in_use, self.budget,
+                                                  self.batch_flops)
                 if not batch:
                     break
-                ready = rest
                 ev0 = torch.cuda.Event(enable_timing=True)
                 ev = torch.cuda.Event(enable_timing=True)
                 if len(batch) == 1 and _key(batch[0]) in self.graphs:
