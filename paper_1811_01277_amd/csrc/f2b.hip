@@ -208,9 +208,18 @@ __global__ __launch_bounds__(kRows) void k_update(E* __restrict__ A, int64_t lda
   const int64_t row = (int64_t)blockIdx.x * kRows + threadIdx.x;
   if (row < m && row >= i) {
     const E v = (row == i) ? from_re<E>(1.0) : V[r0 + row + (p + i) * ldv];
-    for (int64_t j = i + 1; j < b; ++j) {
-      E& a = A[r0 + row + (p + j) * lda];
-      a = sub(a, Num<E>::mul(v, coef[j]));
+    // eight columns loaded before any is written back: the stores could
+    // alias the next loads as far as the compiler knows, which would
+    // otherwise serialise every column's load behind the previous store
+    constexpr int CH = 8;
+    for (int64_t j0 = i + 1; j0 < b; j0 += CH) {
+      E a[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (j0 + u < b) a[u] = A[r0 + row + (p + j0 + u) * lda];
+#pragma unroll
+      for (int u = 0; u < CH; ++u)
+        if (j0 + u < b) A[r0 + row + (p + j0 + u) * lda] = sub(a[u], Num<E>::mul(v, coef[j0 + u]));
     }
     A[r0 + row + (p + i) * lda] = (row == i) ? from_re<E>(shb) : from_re<E>(0.0);
   }
