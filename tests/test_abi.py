@@ -342,3 +342,26 @@ def test_chosen_plan_single_and_batched():
     with pytest.raises(P.ElpaError) as e:
         P.chosen_plan(100, 100, 64, 9)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("dt,nbw,n,nev,path,k", [
+    ("r64", 64, 2999, 2999, "split", 80), ("r64", 64, 3000, 3000, "wy", 128),
+    ("r64", 64, 5999, 5999, "wy", 128), ("r64", 64, 6000, 6000, "wy", 160),
+    ("r64", 64, 20000, 1023, "split", 80), ("r64", 64, 20000, 1024, "wy", 160),
+    ("r32", 64, 5999, 5999, "wy", 96), ("r32", 64, 6000, 6000, "wy", 160),
+    ("r32", 64, 500, 100, "wy", 96), ("c64", 64, 500, 100, "wy", 48),
+    ("r64", 32, 1999, 1999, "split", 64), ("r64", 32, 2000, 2000, "wy", 96),
+    ("r32", 32, 2000, 1023, "split", 64), ("r32", 32, 2000, 1024, "wy", 96),
+    ("c64", 32, 8000, 8000, "split", 48),
+])
+def test_library_choice_boundaries(dt, nbw, n, nev, path, k):
+    """The single-call kernel choice at the edges of its size rules (no tuned
+    plan): compact-WY for fp64 from n = 3000 with nev >= 1024 (k = 160 from
+    n = 6000), fp32 and complex at nbw = 64 (fp32 k = 160 from n = 6000), real
+    data at nbw = 32 from n = 2000 with nev >= 1024; the two-lane kernel
+    otherwise."""
+    P.tuner_clear()
+    code = {"r64": P.R64, "r32": P.R32, "c64": P.C64}[dt]
+    got = P.chosen_plan(n, nev, nbw, code)
+    want = {"split": P.PATH_SPLIT, "wy": P.PATH_WY}[path]
+    assert (got["path"], got["k"]) == (want, k), got
